@@ -1,0 +1,217 @@
+"""ctypes front end of the FP64 CPU oracle (oracle/lbm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product package.  It
+shares no code with the GPU library; both are fed the same `Problem`
+description from the seeded input module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_oracle.so")
+NQ = 19
+
+_lib = None
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("physics", C.c_int), ("forchheimer", C.c_int), ("eps_grad", C.c_int),
+        ("G", C.c_double * 3),
+        ("nu0", C.c_double), ("a0", C.c_double), ("a1", C.c_double), ("alpha", C.c_double),
+        ("cap", C.c_double), ("k1", C.c_double), ("k0", C.c_double),
+        ("tau1", C.c_double), ("tau2", C.c_double), ("tau_d", C.c_double),
+        ("A", C.c_double), ("beta", C.c_double),
+        ("face_kind", C.c_int * 6),
+        ("face_rho", C.c_double * 6), ("face_conc", C.c_double * 6), ("face_angle", C.c_double * 6),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle import build_oracle
+            build_oracle.build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.POINTER(OrcParams), dp, dp, dp, dp, dp]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_step.argtypes = [C.c_void_p, C.c_int]
+        L.orc_step.restype = C.c_int
+        L.orc_steps_done.argtypes = [C.c_void_p]
+        L.orc_steps_done.restype = C.c_long
+        L.orc_moments.argtypes = [C.c_void_p, dp, dp, dp]
+        L.orc_diag.argtypes = [C.c_void_p, dp]
+        L.orc_get_state.argtypes = [C.c_void_p, C.c_int, dp]
+        L.orc_set_state.argtypes = [C.c_void_p, C.c_int, dp, C.c_long]
+        L.orc_step_cells.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_long), dp, dp, dp]
+        L.orc_cell_types.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte)]
+        L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
+        L.orc_feq.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+        L.orc_force.argtypes = [C.c_double, dp, C.c_double, C.c_double, dp, dp]
+        L.orc_heq.argtypes = [C.c_double, dp, dp]
+        L.orc_viscosity.argtypes = [C.POINTER(OrcParams), C.c_double, C.c_double]
+        L.orc_viscosity.restype = C.c_double
+        L.orc_solve_speed.argtypes = [dp, dp, dp]
+        L.orc_solve_speed.restype = C.c_double
+        L.orc_porous_velocity.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _vec(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+
+
+def params_from_problem(p) -> OrcParams:
+    nx, ny, nz = p.shape
+    o = OrcParams()
+    o.nx, o.ny, o.nz = nx, ny, nz
+    o.physics = int(p.physics)
+    o.forchheimer = int(bool(p.forchheimer))
+    o.eps_grad = int(bool(p.eps_grad))
+    o.G = (C.c_double * 3)(*[float(g) for g in p.G])
+    o.nu0, o.a0, o.a1, o.alpha, o.cap, o.k1, o.k0 = (float(p.nu0), float(p.a0), float(p.a1),
+                                                      float(p.alpha), float(p.cap), float(p.k1), float(p.k0))
+    o.tau1, o.tau2, o.tau_d = float(p.tau1), float(p.tau2), float(p.tau_d)
+    o.A, o.beta = float(p.A), float(p.beta)
+    o.face_kind = (C.c_int * 6)(*[int(f.kind) for f in p.faces])
+    o.face_rho = (C.c_double * 6)(*[float(f.rho) for f in p.faces])
+    o.face_conc = (C.c_double * 6)(*[float(f.conc) for f in p.faces])
+    o.face_angle = (C.c_double * 6)(*[float(f.angle) for f in p.faces])
+    return o
+
+
+def lattice():
+    """(velocities (19,3) int, weights (19,), opposite (19,)) in the oracle's order."""
+    v = (C.c_int * (3 * NQ))()
+    w = np.zeros(NQ)
+    o = (C.c_int * NQ)()
+    lib().orc_lattice(v, _dp(w), o)
+    return np.array(v[:], dtype=np.int64).reshape(NQ, 3), w, np.array(o[:], dtype=np.int64)
+
+
+def feq(rho, u, eps, tau, A, F):
+    out = np.zeros(NQ)
+    lib().orc_feq(float(rho), _dp(_vec(u)), float(eps), float(tau), float(A), _dp(_vec(F)), _dp(out))
+    return out
+
+
+def force(rho, u, eps, tau, Fext):
+    out = np.zeros(NQ)
+    lib().orc_force(float(rho), _dp(_vec(u)), float(eps), float(tau), _dp(_vec(Fext)), _dp(out))
+    return out
+
+
+def heq(epsC, vstar):
+    out = np.zeros(NQ)
+    lib().orc_heq(float(epsC), _dp(_vec(vstar)), _dp(out))
+    return out
+
+
+def solve_speed(W, lam, mu):
+    return lib().orc_solve_speed(_dp(_vec(W)), _dp(_vec(lam)), _dp(_vec(mu)))
+
+
+def viscosity(problem, C_, t):
+    prm = params_from_problem(problem)
+    return lib().orc_viscosity(C.byref(prm), float(C_), float(t))
+
+
+def porous_velocity(problem, eps, kinv, nu, V):
+    prm = params_from_problem(problem)
+    Vp = np.zeros(3)
+    Fx = np.zeros(3)
+    lib().orc_porous_velocity(C.byref(prm), float(eps), _dp(_vec(kinv)), float(nu), _dp(_vec(V)),
+                              _dp(Vp), _dp(Fx))
+    return Vp, Fx
+
+
+class Oracle:
+    """Stateful FP64 simulation of one lattice."""
+
+    def __init__(self, problem):
+        p = problem.fill_defaults()
+        self.problem = p
+        self.shape = p.shape
+        nx, ny, nz = p.shape
+        self.n = nx * ny * nz
+        self._keep = [_vec(p.eps).reshape(-1), _vec(p.kinv).reshape(-1), _vec(p.rho0).reshape(-1),
+                      _vec(p.vel0).reshape(-1), _vec(p.c0).reshape(-1)]
+        self.params = params_from_problem(p)
+        h = lib().orc_create(C.byref(self.params), *[_dp(a) for a in self._keep])
+        if not h:
+            raise MemoryError("oracle allocation failed")
+        self.h = C.c_void_p(h)
+        self._keep = None
+
+    def close(self):
+        if self.h:
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        if lib().orc_step(self.h, int(n)) != 0:
+            raise MemoryError("oracle allocation failed")
+        return self
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib().orc_steps_done(self.h))
+
+    def moments(self):
+        """(rho (nz,ny,nx), V' (3,nz,ny,nx), C (nz,ny,nx)) of the last step."""
+        nx, ny, nz = self.shape
+        rho = np.zeros(self.n)
+        vel = np.zeros(3 * self.n)
+        c = np.zeros(self.n)
+        lib().orc_moments(self.h, _dp(rho), _dp(vel), _dp(c))
+        return rho.reshape(nz, ny, nx), vel.reshape(3, nz, ny, nx), c.reshape(nz, ny, nx)
+
+    def diag(self):
+        out = np.zeros(8)
+        lib().orc_diag(self.h, _dp(out))
+        return out
+
+    def cell_types(self):
+        nx, ny, nz = self.shape
+        out = (C.c_ubyte * self.n)()
+        lib().orc_cell_types(self.h, out)
+        return np.frombuffer(out, dtype=np.uint8).copy().reshape(nz, ny, nx)
+
+    def get_state(self, lattice_id: int):
+        out = np.zeros(NQ * self.n)
+        lib().orc_get_state(self.h, int(lattice_id), _dp(out))
+        return out.reshape(NQ, self.n)
+
+    def set_state(self, lattice_id: int, data: np.ndarray, step: int):
+        a = _vec(data).reshape(-1)
+        assert a.size == NQ * self.n
+        lib().orc_set_state(self.h, int(lattice_id), _dp(a), int(step))
+
+    def step_cells(self, cells):
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+        k = cells.size
+        fo = np.zeros(k * NQ)
+        ho = np.zeros(k * NQ)
+        mo = np.zeros(k * 5)
+        lib().orc_step_cells(self.h, k, cells.ctypes.data_as(C.POINTER(C.c_long)), _dp(fo), _dp(ho), _dp(mo))
+        return fo.reshape(k, NQ), ho.reshape(k, NQ), mo.reshape(k, 5)

@@ -1,0 +1,282 @@
+"""Seeded synthetic inputs: problem descriptions and media shaped like the
+workloads of the paper (Poiseuille channels of Sec. 5.1-5.2, the drop of
+Sec. 5.3, the spruce-like ring medium of Sec. 5.5).
+
+This module describes *inputs* only.  It holds none of the update's
+arithmetic and is the one module that both the FP64 oracle (tests) and the
+GPU library (product) are fed from.  Arrays use C order with shape
+(nz, ny, nx), so the flat index is x + nx * (y + ny * z); vector fields carry
+a leading axis of 3.
+
+Random numbers come from a counter-based generator: SplitMix64 (Steele, Lea
+and Flood, OOPSLA 2014) applied to the global cell coordinates and a seed,
+so that a crop of a large medium equals the medium generated for the crop.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+PERIODIC, WALL, RESERVOIR = 0, 1, 2
+SINGLE, MISCIBLE, IMMISCIBLE = 0, 1, 2
+PHYSICS_NAMES = {"single": SINGLE, "miscible": MISCIBLE, "immiscible": IMMISCIBLE}
+
+
+@dataclasses.dataclass
+class Face:
+    kind: int = PERIODIC
+    rho: float = 1.0        # reservoir density
+    conc: float = 0.0       # reservoir concentration
+    angle: float = 90.0     # wall contact angle in degrees (two-fluid model)
+
+
+@dataclasses.dataclass
+class Problem:
+    """Everything needed to set up one lattice: sizes, physics, parameters,
+    boundary faces (-x,+x,-y,+y,-z,+z) and the initial / medium fields."""
+    shape: Tuple[int, int, int]                 # (nx, ny, nz)
+    physics: int = SINGLE
+    G: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    forchheimer: bool = False
+    eps_grad: bool = True
+    # viscosity law nu = nu0 * min(a0 + a1 exp(alpha t), cap) * exp(k1 C + k0)
+    nu0: float = 0.1
+    a0: float = 1.0
+    a1: float = 0.0
+    alpha: float = 0.0
+    cap: float = 1e30
+    k1: float = 0.0
+    k0: float = 0.0
+    tau1: float = 0.7       # two-fluid: fluid 1 (the one carried by the second lattice)
+    tau2: float = 1.0       # two-fluid: fluid 2
+    tau_d: float = 0.65     # solute relaxation time
+    A: float = 0.0          # surface-tension strength
+    beta: float = 0.7       # recolouring strength
+    faces: List[Face] = dataclasses.field(default_factory=lambda: [Face() for _ in range(6)])
+    eps: Optional[np.ndarray] = None    # (nz,ny,nx)
+    kinv: Optional[np.ndarray] = None   # (3,nz,ny,nx)
+    rho0: Optional[np.ndarray] = None   # (nz,ny,nx)
+    vel0: Optional[np.ndarray] = None   # (3,nz,ny,nx)
+    c0: Optional[np.ndarray] = None     # (nz,ny,nx)
+
+    @property
+    def ncell(self) -> int:
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    def fill_defaults(self) -> "Problem":
+        nx, ny, nz = self.shape
+        if self.eps is None:
+            self.eps = np.ones((nz, ny, nx))
+        if self.kinv is None:
+            self.kinv = np.zeros((3, nz, ny, nx))
+        if self.rho0 is None:
+            self.rho0 = np.ones((nz, ny, nx))
+        if self.vel0 is None:
+            self.vel0 = np.zeros((3, nz, ny, nx))
+        if self.c0 is None:
+            self.c0 = np.zeros((nz, ny, nx))
+        return self
+
+    def uniform_medium(self) -> bool:
+        e = self.eps
+        k = self.kinv
+        return bool(np.all(e == e.flat[0]) and all(np.all(k[a] == k[a].flat[0]) for a in range(3)))
+
+
+# --------------------------------------------------------------------------
+# counter-based random numbers
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser applied to uint64 counters (wrapping arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = (x.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def cell_uniform(seed: int, x: np.ndarray, y: np.ndarray, z: np.ndarray, stream: int) -> np.ndarray:
+    """Uniform variate in (0,1) for global cell (x,y,z), a seed and a stream id."""
+    c = (x.astype(np.uint64) | (y.astype(np.uint64) << np.uint64(20))
+         | (z.astype(np.uint64) << np.uint64(40)) | (np.uint64(stream & 0xF) << np.uint64(60)))
+    k = splitmix64(np.asarray([seed], dtype=np.uint64))[0]
+    h = splitmix64(splitmix64(c) ^ k)
+    return ((h >> np.uint64(11)).astype(np.float64) + 0.5) * (1.0 / 9007199254740992.0)
+
+
+def cell_normal(seed: int, x, y, z) -> np.ndarray:
+    """Standard normal variate per global cell (Box-Muller on two streams)."""
+    u1 = cell_uniform(seed, x, y, z, 0)
+    u2 = cell_uniform(seed, x, y, z, 1)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+# --------------------------------------------------------------------------
+# media
+
+def kappa(eps):
+    """Porosity dependence of the wood permeability tensor: with
+    rho/rho_max = 1 - eps the prefactor (rho_max/rho)^2 eps^(11/3) of Eq. Ktensor
+    becomes eps^(11/3) / (1 - eps)^2."""
+    return eps ** (11.0 / 3.0) / (1.0 - eps) ** 2
+
+
+def spruce_medium(shape, seed: int = 0, ratio: float = 100.0, origin=(0, 0, 0),
+                  eps_lo: float = 0.4, eps_hi: float = 0.8, period: float = 32.0,
+                  k_ref: float = 1e-2, sigma: float = 0.3):
+    """Spruce-like banded medium.  x is the radial (ring) axis, y longitudinal,
+    z tangential (the (r, z, theta) frame of Eq. Ktensor).  Porosity varies
+    sinusoidally between eps_lo and eps_hi along x with the ring period;
+    the diagonal permeability is K_ref * kappa(eps)/kappa(eps_mid) *
+    exp(sigma xi) * (1/ratio, 1, 1/ratio) with one seeded standard normal xi per
+    cell.  `origin` is the global coordinate of the crop's first cell.
+    Returns (eps (nz,ny,nx), kinv (3,nz,ny,nx)) in float64."""
+    nx, ny, nz = shape
+    ox, oy, oz = origin
+    x = np.arange(nx, dtype=np.int64) + ox
+    y = np.arange(ny, dtype=np.int64) + oy
+    z = np.arange(nz, dtype=np.int64) + oz
+    mid = 0.5 * (eps_lo + eps_hi)
+    amp = 0.5 * (eps_hi - eps_lo)
+    eps_x = mid + amp * np.sin(2.0 * math.pi * x / period)
+    eps = np.broadcast_to(eps_x[None, None, :], (nz, ny, nx)).copy()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    xi = cell_normal(seed, X, Y, Z)
+    kl = k_ref * kappa(eps) / kappa(mid) * np.exp(sigma * xi)
+    kinv = np.empty((3, nz, ny, nx))
+    kinv[0] = ratio / kl
+    kinv[1] = 1.0 / kl
+    kinv[2] = ratio / kl
+    return eps, kinv
+
+
+# --------------------------------------------------------------------------
+# problems shaped like the paper's workloads
+
+def poiseuille(shape=(32, 32, 32), eps=0.7, K=1e-2, G=1e-6, tau=0.8, wall_axis=2,
+               flow_axis=0, kdiag=None, forchheimer=False) -> Problem:
+    """Body-force driven channel through a homogeneous porous medium between
+    two no-slip walls (Sec. 5.1): solid planes at both ends of `wall_axis`,
+    periodic elsewhere, constant viscosity nu = (tau - 1/2)/3."""
+    nx, ny, nz = shape
+    faces = [Face() for _ in range(6)]
+    faces[2 * wall_axis] = Face(kind=WALL)
+    faces[2 * wall_axis + 1] = Face(kind=WALL)
+    g = [0.0, 0.0, 0.0]
+    g[flow_axis] = G
+    kd = kdiag if kdiag is not None else (K, K, K)
+    kinv = np.empty((3, nz, ny, nx))
+    for a in range(3):
+        kinv[a] = 1.0 / kd[a]
+    p = Problem(shape=tuple(shape), physics=SINGLE, G=tuple(g), forchheimer=forchheimer,
+                nu0=(tau - 0.5) / 3.0, faces=faces,
+                eps=np.full((nz, ny, nx), float(eps)), kinv=kinv)
+    return p.fill_defaults()
+
+
+def hardening_law(p: Problem) -> Problem:
+    """nu = 0.1 exp(2 C) min(exp(1e-4 t), 10): the hardening law of the
+    miscible workloads, a member of the Eq. nuall family."""
+    p.nu0, p.a0, p.a1, p.alpha, p.cap, p.k1, p.k0 = 0.1, 0.0, 1.0, 1e-4, 10.0, 2.0, 0.0
+    return p
+
+
+P_EXT = 0.0441  # applied pressure of the penetration example, Sec. 5.5
+
+
+def miscible(shape=(256, 256, 256), seed=0, ratio=100.0, origin=(0, 0, 0), D=0.05,
+             p_ext=P_EXT, reservoirs=True) -> Problem:
+    """Miscible mixture in the spruce-like medium: hydrodynamic lattice plus the
+    solute lattice (diffusivity D), hardening viscosity, Darcy + Forchheimer
+    drag, inlet reservoir at x = 0 with rho = 1 + 3 p_ext and C = 1, outlet
+    reservoir at x = nx-1 with rho = 1 and C = 0, periodic in y and z."""
+    nx, ny, nz = shape
+    eps, kinv = spruce_medium(shape, seed=seed, ratio=ratio, origin=origin)
+    faces = [Face() for _ in range(6)]
+    if reservoirs:
+        faces[0] = Face(kind=RESERVOIR, rho=1.0 + 3.0 * p_ext, conc=1.0)
+        faces[1] = Face(kind=RESERVOIR, rho=1.0, conc=0.0)
+    p = Problem(shape=tuple(shape), physics=MISCIBLE, forchheimer=True, tau_d=0.5 + 3.0 * D,
+                faces=faces, eps=eps, kinv=kinv)
+    hardening_law(p)
+    return p.fill_defaults()
+
+
+def drop(shape=(128, 128, 128), radius=20.0, centre=None, speed=0.05, tau1=0.7, tau2=1.0,
+         A=0.01, beta=0.7, bottom_angle=120.0, top_angle=90.0, walls=True) -> Problem:
+    """Two-fluid drop moving toward a hydrophobic plane (Sec. 5.3 set-up, two-fluid
+    form): a sharp sphere of fluid 1 (C = 1) of the given radius, moving with
+    velocity -speed along z, walls at z = 0 (bottom_angle) and z = nz-1
+    (top_angle), periodic in x and y, no porous medium (eps = 1, K^-1 = 0)."""
+    nx, ny, nz = shape
+    if centre is None:
+        centre = (nx // 2, ny // 2, nz // 2)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2
+    inside = r2 <= radius * radius
+    c0 = inside.astype(np.float64)
+    vel0 = np.zeros((3, nz, ny, nx))
+    vel0[2][inside] = -speed
+    faces = [Face() for _ in range(6)]
+    if walls:
+        faces[4] = Face(kind=WALL, angle=bottom_angle)
+        faces[5] = Face(kind=WALL, angle=top_angle)
+    p = Problem(shape=tuple(shape), physics=IMMISCIBLE, tau1=tau1, tau2=tau2, A=A, beta=beta,
+                faces=faces, c0=c0, vel0=vel0)
+    return p.fill_defaults()
+
+
+# --------------------------------------------------------------------------
+# serving workload: a stream of solve requests
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the stream
+    edge: int               # cubic domain edge
+    physics: int
+    steps: int
+    ratio: float
+    seed: int
+
+
+def request_stream(n=64, rate=4.0, edge_lo=48, edge_hi=192, p_miscible=0.7,
+                   steps_lo=500, steps_hi=5000, ratio_lo=10.0, ratio_hi=200.0,
+                   arrival_seed=1, param_seed=2, medium_seed0=1000) -> List[Request]:
+    """Poisson arrivals at `rate` per second; edge log-uniform in
+    [edge_lo, edge_hi]; physics miscible with probability p_miscible, else
+    two-fluid; steps uniform in [steps_lo, steps_hi]; anisotropy ratio uniform
+    in [ratio_lo, ratio_hi]."""
+    ra = np.random.default_rng(arrival_seed)
+    rp = np.random.default_rng(param_seed)
+    t = np.cumsum(ra.exponential(1.0 / rate, size=n))
+    out = []
+    for i in range(n):
+        u = rp.random()
+        edge = int(round(edge_lo * (edge_hi / edge_lo) ** u))
+        phys = MISCIBLE if rp.random() < p_miscible else IMMISCIBLE
+        steps = int(rp.integers(steps_lo, steps_hi + 1))
+        ratio = float(rp.uniform(ratio_lo, ratio_hi))
+        out.append(Request(rid=i, arrival=float(t[i]), edge=edge, physics=phys, steps=steps,
+                           ratio=ratio, seed=medium_seed0 + i))
+    return out
+
+
+def request_problem(req: Request) -> Problem:
+    """The lattice a serving request asks for: the miscible workload at its
+    edge and anisotropy, or a drop of radius 20 N / 128 in that request's
+    medium."""
+    n = req.edge
+    if req.physics == MISCIBLE:
+        return miscible((n, n, n), seed=req.seed, ratio=req.ratio)
+    p = drop((n, n, n), radius=round(20.0 * n / 128.0))
+    eps, kinv = spruce_medium((n, n, n), seed=req.seed, ratio=req.ratio)
+    p.eps, p.kinv = eps, kinv
+    return p
