@@ -1,0 +1,162 @@
+"""Benchmark of the porous-media lattice Boltzmann step on one MI355X.
+
+Workload (default): the miscible mixture at 256^3 in FP32 -- hydrodynamic
+lattice plus solute lattice (D = 0.05) in the seeded spruce-like medium
+(porosity 0.4-0.8 sinusoidal along x with period 32, diagonal permeability
+100:1:1 with lognormal noise sigma 0.3), hardening viscosity
+nu = 0.1 e^{2C} min(e^{1e-4 t}, 10), Darcy + Forchheimer drag, pressure inlet
+reservoir at x = 0 (C = 1) and outlet at x = 255.  One step = one pass of the
+whole update over the lattice (stream + collide of both lattices; FP64
+diagnostics every 100 steps).
+
+Prints one JSON line: MLUPS (million lattice-cell updates per second),
+the roofline of the step kernel (algorithmic bytes per launch / measured
+kernel time vs 8 TB/s HBM peak), the same run with BF16- and FP16-stored
+populations, and the FP64 CPU oracle timed on the host on a bounded sample.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N]
+                       [--storage f32] [--no-cpu-baseline] [--no-reduced]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per lattice update of the miscible step: both lattices
+# read and written once (2 x 19 x 2 populations) + porosity + 3 K^-1 values
+def bytes_per_lup(storage_bytes, real_bytes=4):
+    return 2 * 19 * 2 * storage_bytes + 4 * real_bytes
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ensure_built():
+    from paper_0912_4230_amd import binding
+    from oracle import oracle
+    if not os.path.exists(binding.LIB_PATH) or not os.path.exists(oracle.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def time_gpu(problem, storage, steps, warmup):
+    import torch
+    from paper_0912_4230_amd.sim import Simulation
+    sim = Simulation(problem, storage=storage, diag_every=100)
+    stream = sim.stream
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    dg = sim.diag(check=False)
+    sim.close()
+    return ms, dg
+
+
+def cpu_baseline(budget_s=15.0):
+    """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
+    seeded medium, as many steps as fit in about budget_s seconds."""
+    from oracle import oracle as O
+    from paper_0912_4230_amd import inputs as I
+    p = I.miscible(shape=(64, 64, 64), seed=0)
+    o = O.Oracle(p)
+    o.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(5)
+        n += 5
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 64 ** 3 * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"miscible physics, 64^3 crop of the seeded medium, {n} steps, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reduced", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the lattice update is not sharded across GPUs in this "
+              "build (see the design notes for the slab decomposition); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    ensure_built()
+    from paper_0912_4230_amd import inputs as I
+    from paper_0912_4230_amd import binding as B
+
+    n = args.size
+    log(f"bench: generating the {n}^3 seeded medium")
+    p = I.miscible(shape=(n, n, n), seed=0)
+    ncell = n ** 3
+    sb = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.storage]
+    rb = 8 if args.storage == "f64" else 4
+
+    log(f"bench: {args.storage} {n}^3 warmup {args.warmup} steps {args.steps}")
+    ms, dg = time_gpu(p, args.storage, args.steps, args.warmup)
+    ms_step = ms / args.steps
+    mlups = ncell * args.steps / (ms / 1e3) / 1e6
+    bpl = bytes_per_lup(sb, rb)
+    achieved = bpl * ncell / (ms_step / 1e3) / 1e9
+    log(f"bench: {ms_step:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
+
+    out = {
+        "metric": "MLUPS",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic (seeded spruce-like medium)",
+        "config": {"workload": f"miscible mixture {n}^3, {args.storage} populations, D=0.05, "
+                               "spruce-like medium 100:1:1, hardening viscosity, Darcy+Forchheimer, "
+                               "inlet/outlet reservoirs", "grid": [n, n, n], "cells": ncell,
+                   "diag_every": 100},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_lup": bpl, "kernel": "k_step<miscible>"},
+        "diag_final": {"sum_rho": dg[0], "sum_epsC": dg[4], "max_v": dg[6], "nonfinite": dg[7]},
+    }
+    if not args.no_reduced and args.storage == "f32":
+        red = {}
+        for st in ("bf16", "f16"):
+            ms2, dg2 = time_gpu(p, st, args.steps, args.warmup)
+            s2 = ms2 / args.steps
+            b2 = bytes_per_lup(2, 4)
+            red[st] = {"MLUPS": round(ncell * args.steps / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(s2, 5),
+                       "bytes_per_lup": b2, "achieved_GBs": round(b2 * ncell / (s2 / 1e3) / 1e9, 1),
+                       "speedup_vs_f32": round(ms_step / s2, 3)}
+            log(f"bench: {st}: {s2:.4f} ms/step, speedup {ms_step / s2:.3f}")
+        out["reduced_storage"] = red
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) porous-media lattice Boltzmann library.
+ *
+ * The library advances the 3D lattice Boltzmann model of Mendoza, Wittel and
+ * Herrmann, "Simulation of Flow of Mixtures Through Anisotropic Porous Media
+ * using a Lattice Boltzmann Model" (arXiv:0912.4230) on one GPU:
+ *   - a D3Q19 hydrodynamic lattice with BGK collision and forcing terms for
+ *     the porous medium (Sec. 2.1, Eqs. lbe2, coeffforce1, forcement,
+ *     expandV, expandVsub, equilc1, equilc2): porosity eps, a diagonal
+ *     anisotropic permeability K, body force G, Darcy drag and (optionally) a
+ *     Forchheimer drag, with a local viscosity nu(C, t) for hardening fluids
+ *     (family of Eq. nuall);
+ *   - a second D3Q19 lattice that is either the solute of a miscible mixture
+ *     (Sec. 2.2, Eqs. equild, boltzeqD) or fluid 1 of a two-fluid
+ *     (immiscible) mixture whose colour gradient (Eq. macros) drives the
+ *     surface-tension term of Eqs. equilc1/2 (tensor of Eq. eqsurftens);
+ *   - walls (halfway bounce-back, with a wall colour that sets the contact
+ *     angle in two-fluid mode), fixed-state reservoirs (pressure inlet /
+ *     outlet) and periodic faces (Sec. 4, boundary conditions).
+ *
+ * One time step follows the simulation procedure of Sec. 4 (flowchart):
+ * stream both lattices, take the moments, form the colour gradient, collide.
+ *
+ * Memory: the library never allocates or frees device memory.  The caller
+ * allocates one device workspace of lbm_workspace_bytes() bytes (for example
+ * a torch uint8 tensor) and owns it; the handle keeps a pointer to it until
+ * lbm_destroy().  All field pointers passed to the library are device
+ * pointers unless stated otherwise.
+ *
+ * Layout of every field: structure of arrays, x fastest,
+ * idx = x + nx * (y + ny * z); a vector field is 3 consecutive planes of
+ * nx*ny*nz values (x, y, z components).  The real type of fields ("real")
+ * is double when storage == LBM_F64 and float otherwise.
+ *
+ * Errors: every call returns an lbm_status; no call aborts or throws.
+ * Argument checks happen before any GPU call.  Kernel faults are reported by
+ * the next call that synchronises (lbm_set_medium, lbm_moments).
+ *
+ * Threading: a handle is used by one host thread at a time.  All work of a
+ * handle is issued on the HIP stream given to lbm_create (NULL = default).
+ */
+#ifndef PORO_LBM_H
+#define PORO_LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,     /* an argument is out of range or inconsistent */
+    LBM_ENOMEM = 2,     /* the workspace is too small */
+    LBM_EDEVICE = 3,    /* a HIP runtime call or a kernel launch failed */
+    LBM_EUNSTABLE = 4,  /* the diagnostics found a non-finite moment */
+    LBM_ESTATE = 5      /* call out of order (e.g. lbm_step before lbm_set_medium) */
+} lbm_status;
+
+typedef enum {
+    LBM_SINGLE = 0,      /* hydrodynamic lattice only */
+    LBM_MISCIBLE = 1,    /* + solute lattice (Sec. 2.2) */
+    LBM_IMMISCIBLE = 2   /* + fluid-1 lattice of a two-fluid colour model */
+} lbm_physics;
+
+typedef enum {
+    LBM_F64 = 0,         /* populations and fields in double */
+    LBM_F32 = 1,         /* populations and fields in float */
+    LBM_BF16_DEV = 2,    /* populations stored in bfloat16, compute in float */
+    LBM_F16_DEV = 3      /* populations stored in IEEE half, compute in float */
+} lbm_storage;
+/* The hydrodynamic populations are stored as deviations f_i - w_i from the
+ * rest-state weights in every storage mode (in reduced precision this is
+ * what makes 16-bit storage usable); the second lattice is stored as is.
+ * Rounding to 16 bits is round-to-nearest-even. */
+
+typedef enum {
+    LBM_FACE_PERIODIC = 0,   /* both faces of an axis must be periodic together */
+    LBM_FACE_WALL = 1,       /* the boundary plane of cells is solid */
+    LBM_FACE_RESERVOIR = 2   /* the boundary plane holds a fixed equilibrium state */
+} lbm_face_kind;
+
+typedef struct {
+    int kind;                   /* lbm_face_kind */
+    double rho;                 /* RESERVOIR: density (pressure p = rho / 3 / eps) */
+    double conc;                /* RESERVOIR: concentration C of the reservoir */
+    double contact_angle_deg;   /* WALL, two-fluid mode: contact angle of fluid 1 */
+} lbm_face;
+
+typedef struct {
+    int nx, ny, nz;             /* cells per axis, each >= 1 (>= 3 on a non-periodic axis) */
+    int physics;                /* lbm_physics */
+    int storage;                /* lbm_storage */
+    int forchheimer;            /* 1: Forchheimer drag -eps F_eps |V'| K^-1/2 V',
+                                   F_eps = 1.75 / sqrt(150 eps^3) */
+    int eps_gradient;           /* 1: solute drift V* = V' + D grad(eps)/eps (Eq. equild) */
+    double G[3];                /* body force (acceleration), lattice units */
+    /* viscosity (single / miscible): nu = nu0 * min(a0 + a1 e^{alpha t}, cap)
+       * e^{k1 C + k0}, t = index of the step being computed; tau = 1/2 + 3 nu.
+       The paper's Eq. nuall is (nu_g, 1, a, alpha, inf, -beta, beta). */
+    double nu0, a0, a1, alpha, cap, k1, k0;
+    double tau1, tau2;          /* two-fluid: relaxation times of fluid 1 and 2;
+                                   nu = C nu_1 + (1 - C) nu_2 with C = rho_1 / rho */
+    double tau_d;               /* miscible: solute relaxation time, D = (tau_d - 1/2)/3 */
+    double A;                   /* two-fluid: surface-tension strength (Eq. equilc1) */
+    double beta;                /* two-fluid: recolouring strength in [0, 1] */
+    lbm_face face[6];           /* order: -x, +x, -y, +y, -z, +z */
+    int diag_every;             /* FP64 diagnostics every k steps (0: only at the end
+                                   of each lbm_step call) */
+} lbm_desc;
+
+/* Medium and initial fields (flowchart of Sec. 4: set rho, V, C, the
+ * porosity and the permeability).  Device pointers of the real type; NULL
+ * selects the uniform value.  The library copies them into the workspace on
+ * the handle's stream; the caller may reuse the buffers once that stream has
+ * passed the call (lbm_set_medium synchronises before returning). */
+typedef struct {
+    const void *eps;            /* ncell values in (0, 1]; NULL: eps_uniform */
+    const void *kinv;           /* 3 planes: 1/K_xx, 1/K_yy, 1/K_zz >= 0; NULL: kinv_uniform */
+    const void *rho0;           /* ncell initial densities > 0; NULL: 1 */
+    const void *vel0;           /* 3 planes, initial velocity V' ; NULL: 0 */
+    const void *c0;             /* ncell initial concentrations; NULL: 0 */
+    double eps_uniform;
+    double kinv_uniform[3];
+} lbm_medium;
+
+typedef struct lbm_sim *lbm_t;
+
+/* Bytes of device workspace a lattice of this description needs; 0 if the
+ * description is invalid. */
+size_t lbm_workspace_bytes(const lbm_desc *d);
+
+/* Validate d, lay the lattice out in dev_workspace (>= lbm_workspace_bytes(d)
+ * bytes, 256-byte aligned, owned by the caller) and return a host handle.
+ * hip_stream is a hipStream_t (NULL: default stream).  No GPU call is made
+ * when the arguments are rejected. */
+lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes,
+                      void *hip_stream, lbm_t *out);
+
+/* Copy the medium and the initial fields in and set the populations to their
+ * equilibria (Eqs. equilc1/2, equild; two-fluid: g = C f).  Validates the
+ * fields on the device (eps in (0,1], K^-1 >= 0, rho0 > 0, all finite) and
+ * returns LBM_EINVAL if a value is out of range.  Resets the step count.
+ * Synchronises the handle's stream. */
+lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the handle's stream. */
+lbm_status lbm_step(lbm_t h, int nsteps);
+
+/* Advance n lattices by nsteps[i] steps each, with one kernel launch per
+ * step for all lattices of the same physics and storage (continuous
+ * batching).  All handles must share one stream.  Per-lattice results are
+ * bitwise identical to lbm_step on the same handle. */
+lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n);
+
+/* Copy the moments of the last step (density rho, corrected velocity V' as
+ * 3 planes, concentration C; after 0 steps: the initial fields) into caller
+ * device buffers of the real type (each may be NULL), and the FP64
+ * diagnostics of the last diagnostic step into the host array diag (may be
+ * NULL): {Sum rho, Sum rho V'_x, Sum rho V'_y, Sum rho V'_z, Sum eps C
+ * (miscible) or Sum rho_1 (two-fluid) or 0, |V' - V'_prev|^2 / |V'|^2
+ * relative to the previous diagnostic, max |V'|, count of non-finite cells},
+ * all over fluid cells.  Solid cells read 0; reservoir cells read their fixed
+ * state.  Synchronises the stream; returns LBM_EUNSTABLE when the count of
+ * non-finite cells is not zero. */
+lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8]);
+
+/* Current post-collision populations of lattice 0 (hydrodynamic, as
+ * deviations f_i - w_i) or 1 (second lattice, as is), decoded to the real
+ * type: 19 planes in the direction order of lbm_lattice(). */
+lbm_status lbm_populations(lbm_t h, int lattice, void *dst);
+
+/* Completed steps since lbm_set_medium, or -1 for a NULL handle. */
+long long lbm_steps_done(lbm_t h);
+
+/* Free the host handle (the workspace stays the caller's). */
+lbm_status lbm_destroy(lbm_t h);
+
+/* The library's D3Q19 direction order: vel[3*q + a], weights w[q]. */
+void lbm_lattice(int vel[57], double w[19]);
+
+/* Static text for a status code. */
+const char *lbm_strerror(lbm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PORO_LBM_H */

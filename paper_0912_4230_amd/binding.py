@@ -1,0 +1,157 @@
+"""ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  The shared
+library libporolbm.so sits next to this file (built by build_lib.py); if it
+is missing, loading raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libporolbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = range(6)
+LBM_SINGLE, LBM_MISCIBLE, LBM_IMMISCIBLE = range(3)
+LBM_F64, LBM_F32, LBM_BF16_DEV, LBM_F16_DEV = range(4)
+LBM_FACE_PERIODIC, LBM_FACE_WALL, LBM_FACE_RESERVOIR = range(3)
+
+STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV}
+EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_medium", "lbm_step", "lbm_step_batch",
+            "lbm_moments", "lbm_populations", "lbm_steps_done", "lbm_destroy", "lbm_lattice",
+            "lbm_strerror"]
+
+
+class lbm_face(C.Structure):
+    _fields_ = [("kind", C.c_int), ("rho", C.c_double), ("conc", C.c_double),
+                ("contact_angle_deg", C.c_double)]
+
+
+class lbm_desc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("physics", C.c_int), ("storage", C.c_int),
+        ("forchheimer", C.c_int), ("eps_gradient", C.c_int),
+        ("G", C.c_double * 3),
+        ("nu0", C.c_double), ("a0", C.c_double), ("a1", C.c_double), ("alpha", C.c_double),
+        ("cap", C.c_double), ("k1", C.c_double), ("k0", C.c_double),
+        ("tau1", C.c_double), ("tau2", C.c_double), ("tau_d", C.c_double),
+        ("A", C.c_double), ("beta", C.c_double),
+        ("face", lbm_face * 6),
+        ("diag_every", C.c_int),
+    ]
+
+
+class lbm_medium(C.Structure):
+    _fields_ = [("eps", C.c_void_p), ("kinv", C.c_void_p), ("rho0", C.c_void_p),
+                ("vel0", C.c_void_p), ("c0", C.c_void_p), ("eps_uniform", C.c_double),
+                ("kinv_uniform", C.c_double * 3)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lbm_strerror(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libporolbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.lbm_workspace_bytes.restype = C.c_size_t
+        L.lbm_workspace_bytes.argtypes = [C.POINTER(lbm_desc)]
+        L.lbm_create.restype = C.c_int
+        L.lbm_create.argtypes = [C.POINTER(lbm_desc), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_set_medium.restype = C.c_int
+        L.lbm_set_medium.argtypes = [vp, C.POINTER(lbm_medium)]
+        L.lbm_step.restype = C.c_int
+        L.lbm_step.argtypes = [vp, C.c_int]
+        L.lbm_step_batch.restype = C.c_int
+        L.lbm_step_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), C.c_int]
+        L.lbm_moments.restype = C.c_int
+        L.lbm_moments.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+        L.lbm_populations.restype = C.c_int
+        L.lbm_populations.argtypes = [vp, C.c_int, vp]
+        L.lbm_steps_done.restype = C.c_longlong
+        L.lbm_steps_done.argtypes = [vp]
+        L.lbm_destroy.restype = C.c_int
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_lattice.restype = None
+        L.lbm_lattice.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.lbm_strerror.restype = C.c_char_p
+        L.lbm_strerror.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str) -> int:
+    if status != LBM_OK:
+        raise LbmError(status, where)
+    return status
+
+
+def lbm_workspace_bytes(desc: lbm_desc) -> int:
+    return int(lib().lbm_workspace_bytes(C.byref(desc)))
+
+
+def lbm_create(desc: lbm_desc, workspace_ptr: int, ws_bytes: int, stream_ptr: int = 0):
+    """Returns the handle (a c_void_p); raises LbmError on failure."""
+    h = C.c_void_p()
+    _check(lib().lbm_create(C.byref(desc), C.c_void_p(workspace_ptr), C.c_size_t(ws_bytes),
+                            C.c_void_p(stream_ptr), C.byref(h)), "lbm_create")
+    return h
+
+
+def lbm_set_medium(h, medium: lbm_medium) -> int:
+    return _check(lib().lbm_set_medium(h, C.byref(medium)), "lbm_set_medium")
+
+
+def lbm_step(h, nsteps: int) -> int:
+    return _check(lib().lbm_step(h, int(nsteps)), "lbm_step")
+
+
+def lbm_step_batch(handles, nsteps) -> int:
+    n = len(handles)
+    hs = (C.c_void_p * n)(*[hh.value for hh in handles])
+    ns = (C.c_int * n)(*[int(s) for s in nsteps])
+    return _check(lib().lbm_step_batch(hs, ns, n), "lbm_step_batch")
+
+
+def lbm_moments(h, rho_ptr: int = 0, vel_ptr: int = 0, conc_ptr: int = 0, diag=None, check=True):
+    """diag: a ctypes c_double*8 array or None.  Returns the status."""
+    st = lib().lbm_moments(h, C.c_void_p(rho_ptr or None), C.c_void_p(vel_ptr or None),
+                           C.c_void_p(conc_ptr or None), diag)
+    if check:
+        _check(st, "lbm_moments")
+    return st
+
+
+def lbm_populations(h, lattice: int, dst_ptr: int) -> int:
+    return _check(lib().lbm_populations(h, int(lattice), C.c_void_p(dst_ptr)), "lbm_populations")
+
+
+def lbm_steps_done(h) -> int:
+    return int(lib().lbm_steps_done(h))
+
+
+def lbm_destroy(h) -> int:
+    return _check(lib().lbm_destroy(h), "lbm_destroy")
+
+
+def lbm_lattice():
+    v = (C.c_int * 57)()
+    w = (C.c_double * 19)()
+    lib().lbm_lattice(v, w)
+    return [tuple(v[3 * q:3 * q + 3]) for q in range(19)], list(w)
+
+
+def lbm_strerror(status: int) -> str:
+    return lib().lbm_strerror(int(status)).decode()

@@ -1,0 +1,87 @@
+// d3q19.hpp -- D3Q19 velocity set and population storage codecs for gfx950.
+//
+// Direction order used on the GPU: 0 rest; 1..6 the axis vectors
+// (+x,-x,+y,-y,+z,-z); 7..18 the twelve face diagonals, each followed by its
+// opposite.  Weights: 1/3 (rest), 1/18 (axes), 1/36 (diagonals), Sec. 2.1 of
+// the paper (sentence after Eq. equilc2).  Components are encoded in bit
+// masks so that every lookup folds to a constant after loop unrolling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace plbm {
+
+constexpr int NQ = 19;
+
+constexpr uint32_t bit(int q) { return 1u << q; }
+constexpr uint32_t XP = bit(1) | bit(7) | bit(9) | bit(11) | bit(13);
+constexpr uint32_t XN = bit(2) | bit(8) | bit(10) | bit(12) | bit(14);
+constexpr uint32_t YP = bit(3) | bit(7) | bit(10) | bit(15) | bit(17);
+constexpr uint32_t YN = bit(4) | bit(8) | bit(9) | bit(16) | bit(18);
+constexpr uint32_t ZP = bit(5) | bit(11) | bit(14) | bit(15) | bit(18);
+constexpr uint32_t ZN = bit(6) | bit(12) | bit(13) | bit(16) | bit(17);
+
+__host__ __device__ constexpr int cx(int q) { return int((XP >> q) & 1u) - int((XN >> q) & 1u); }
+__host__ __device__ constexpr int cy(int q) { return int((YP >> q) & 1u) - int((YN >> q) & 1u); }
+__host__ __device__ constexpr int cz(int q) { return int((ZP >> q) & 1u) - int((ZN >> q) & 1u); }
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr int speed2(int q) { return cx(q) * cx(q) + cy(q) * cy(q) + cz(q) * cz(q); }
+
+template <class R>
+__host__ __device__ constexpr R weight(int q)
+{
+    return q == 0 ? R(1) / R(3) : (q <= 6 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// ---------------------------------------------------------------------------
+// storage codecs: Codec<S>::R is the compute type, load/store convert.
+
+struct bf16_t { uint16_t v; };
+struct f16_t { uint16_t v; };
+
+template <class S> struct Codec;
+
+template <> struct Codec<double> {
+    using R = double;
+    __device__ static R load(const double *p) { return *p; }
+    __device__ static void store(double *p, R v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <> struct Codec<float> {
+    using R = float;
+    __device__ static R load(const float *p) { return *p; }
+    __device__ static void store(float *p, R v) { __builtin_nontemporal_store(v, p); }
+};
+
+// bfloat16: the upper half of an IEEE float; encode rounds to nearest even.
+template <> struct Codec<bf16_t> {
+    using R = float;
+    __device__ static R load(const bf16_t *p)
+    {
+        return __uint_as_float(uint32_t(p->v) << 16);
+    }
+    __device__ static uint16_t encode(float f)
+    {
+        uint32_t u = __float_as_uint(f);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    }
+    __device__ static void store(bf16_t *p, R v)
+    {
+        __builtin_nontemporal_store(encode(v), &p->v);
+    }
+};
+
+// IEEE binary16: hardware conversion (round to nearest even).
+template <> struct Codec<f16_t> {
+    using R = float;
+    __device__ static R load(const f16_t *p) { return float(__builtin_bit_cast(_Float16, p->v)); }
+    __device__ static void store(f16_t *p, R v)
+    {
+        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, _Float16(v)), &p->v);
+    }
+};
+
+}  // namespace plbm

@@ -1,0 +1,795 @@
+// kernels.hpp -- gfx950 kernels of the porous-media lattice Boltzmann step.
+//
+// One thread per lattice cell, 256 threads (four wave64) per block, blocks
+// over the flattened cell index so that every population plane is read and
+// written in contiguous, coalesced runs along x.  Populations are
+// structure-of-arrays [19][nz][ny][nx] in two copies (A-B): a step pulls from
+// the copy holding step n and writes step n+1 into the other one, so each
+// population is read once and written once per step and no cell waits for
+// another.  The hot path is bound by HBM bandwidth, not arithmetic; there is
+// no dense contraction, hence no MFMA.
+//
+// Paper references: Sec. 2.1 (Eqs. macros1, macros, lbe2, coeffforce1,
+// forcement, expandV, expandVsub, equilc1, equilc2), Sec. 2.2 (Eqs. equild,
+// boltzeqD), Sec. 4 (order of the operations of a step), Eq. nuall (local
+// viscosity).
+#pragma once
+
+#include "d3q19.hpp"
+
+namespace plbm {
+
+enum { PH_SINGLE = 0, PH_MISCIBLE = 1, PH_IMMISCIBLE = 2 };
+enum { CELL_FLUID = 0, CELL_SOLID = 1, CELL_RES = 2 };
+
+constexpr int BLOCK = 256;
+constexpr int MAXB = 64;     // lattices per batched launch
+constexpr int NPART = 9;     // diagnostic partial sums per block
+
+// Per-lattice parameters, resident in the lattice's workspace.
+struct LatDev {
+    int nx, ny, nz;
+    int ncell;
+    int nblocks;
+    int physics;
+    int forch, eps_grad;
+    int uniform_eps, uniform_kinv;
+    int wall_lo[3], wall_hi[3], res_lo[3], res_hi[3];
+    double eps_u, kinv_u[3];
+    double G[3];
+    double k1, k0;              // viscosity law, per-cell factor e^{k1 C + k0}
+    double nu1, nu2;            // two-fluid viscosities
+    double tau_d, D;            // solute relaxation time and diffusivity
+    double A, beta;             // surface tension, recolouring
+    double face_rho[6], face_conc[6], face_cw[6];
+    void *f[2];                 // hydrodynamic populations (deviations f - w), copies A, B
+    void *h[2];                 // second lattice (solute h or fluid-1 g), copies A, B
+    void *eps, *kinv, *mom, *rho1;
+    double *partials, *diag;
+    int *err;
+};
+
+// Arguments of one batched launch: lattice l owns logical blocks
+// [blk_start[l], blk_start[l+1]).  flags bit 0: copy holding step n; bit 1:
+// write the moments and the FP64 diagnostics of this step.  nuc: the uniform
+// factor nu0 * min(a0 + a1 e^{alpha t}, cap) of the step being computed.
+struct BatchArgs {
+    int n, total_blocks;
+    int blk_start[MAXB + 1];
+    int flags[MAXB];
+    const LatDev *lat[MAXB];
+    double nuc[MAXB];
+};
+
+// Hardware dispatch places block b on XCD b mod 8.  Map hardware blocks to
+// logical blocks so that each XCD works through one contiguous range of the
+// lattice: neighbouring cells (halo reads of scalar fields) then share the
+// XCD's L2.
+__device__ inline int xcd_remap(int b, int nb)
+{
+    const int X = 8;
+    int q = nb / X, r = nb - q * X;
+    int xcd = b % X, slot = b / X;
+    return xcd * q + min(xcd, r) + slot;
+}
+
+__device__ inline int find_lattice(const BatchArgs &a, int gb)
+{
+    int l = 0;
+    while (l + 1 < a.n && gb >= a.blk_start[l + 1]) ++l;
+    return l;
+}
+
+__device__ inline int cell_type(const LatDev *L, int x, int y, int z, int &face)
+{
+    const int c[3] = {x, y, z};
+    const int n[3] = {L->nx, L->ny, L->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (L->wall_lo[a] && c[a] == 0) { face = 2 * a; return CELL_SOLID; }
+        if (L->wall_hi[a] && c[a] == n[a] - 1) { face = 2 * a + 1; return CELL_SOLID; }
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (L->res_lo[a] && c[a] == 0) { face = 2 * a; return CELL_RES; }
+        if (L->res_hi[a] && c[a] == n[a] - 1) { face = 2 * a + 1; return CELL_RES; }
+    }
+    face = -1;
+    return CELL_FLUID;
+}
+
+// Neighbourhood of a fluid cell: wrapped coordinates of x-1 / x+1 etc. as
+// flat offsets, and whether the cell beyond each face of the cell is solid.
+// A fluid cell is never on a wall or reservoir plane, so on non-periodic axes
+// x-1 and x+1 are always inside the box.
+struct Nbr {
+    uint32_t xm, x0, xp;        // x offsets
+    uint32_t ym, y0, yp;        // y * nx
+    uint32_t zm, z0, zp;        // z * nx * ny
+    bool sxm, sxp, sym, syp, szm, szp;
+};
+
+__device__ inline Nbr neighbours(const LatDev *L, int x, int y, int z)
+{
+    Nbr b;
+    const uint32_t nx = L->nx, ny = L->ny, nz = L->nz, nxy = nx * ny;
+    b.x0 = x;
+    b.xm = x ? x - 1 : nx - 1;
+    b.xp = (uint32_t)x + 1 < nx ? x + 1 : 0;
+    b.y0 = y * nx;
+    b.ym = (y ? y - 1 : ny - 1) * nx;
+    b.yp = ((uint32_t)y + 1 < ny ? y + 1 : 0) * nx;
+    b.z0 = z * nxy;
+    b.zm = (z ? z - 1 : nz - 1) * nxy;
+    b.zp = ((uint32_t)z + 1 < nz ? z + 1 : 0) * nxy;
+    b.sxm = L->wall_lo[0] && x == 1;
+    b.sxp = L->wall_hi[0] && (uint32_t)x + 2 == nx;
+    b.sym = L->wall_lo[1] && y == 1;
+    b.syp = L->wall_hi[1] && (uint32_t)y + 2 == ny;
+    b.szm = L->wall_lo[2] && z == 1;
+    b.szp = L->wall_hi[2] && (uint32_t)z + 2 == nz;
+    return b;
+}
+
+// offset of the cell x + s*v_q (s = +1 or -1)
+template <int Q, int SIGN>
+__device__ inline uint32_t shifted(const Nbr &b)
+{
+    constexpr int sx = SIGN * cx(Q), sy = SIGN * cy(Q), sz = SIGN * cz(Q);
+    const uint32_t ox = sx > 0 ? b.xp : (sx < 0 ? b.xm : b.x0);
+    const uint32_t oy = sy > 0 ? b.yp : (sy < 0 ? b.ym : b.y0);
+    const uint32_t oz = sz > 0 ? b.zp : (sz < 0 ? b.zm : b.z0);
+    return ox + oy + oz;
+}
+
+// is the source x - v_q of the pull solid?
+template <int Q>
+__device__ inline bool source_solid(const Nbr &b)
+{
+    constexpr int sx = -cx(Q), sy = -cy(Q), sz = -cz(Q);
+    bool s = false;
+    if (sx < 0) s = s || b.sxm;
+    if (sx > 0) s = s || b.sxp;
+    if (sy < 0) s = s || b.sym;
+    if (sy > 0) s = s || b.syp;
+    if (sz < 0) s = s || b.szm;
+    if (sz > 0) s = s || b.szp;
+    return s;
+}
+
+// Pull streaming (Eqs. lbe2, boltzeqD): f_q(x) = f~_q(x - v_q), or
+// f~_opp(q)(x) when x - v_q is solid (halfway bounce-back).
+template <class S, int Q>
+__device__ inline typename Codec<S>::R pull_one(const S *__restrict__ P, size_t n, uint32_t idx, const Nbr &b)
+{
+    const bool solid = source_solid<Q>(b);
+    const size_t off = solid ? size_t(opp(Q)) * n + idx : size_t(Q) * n + shifted<Q, -1>(b);
+    return Codec<S>::load(P + off);
+}
+
+template <class S, int Q = 0>
+__device__ inline void pull_all(const S *__restrict__ P, size_t n, uint32_t idx, const Nbr &b,
+                                typename Codec<S>::R *out)
+{
+    out[Q] = pull_one<S, Q>(P, n, idx, b);
+    if constexpr (Q + 1 < NQ) pull_all<S, Q + 1>(P, n, idx, b, out);
+}
+
+// grad(eps)/eps by 3 sum_q w_q eps(x + v_q) v_q / eps(x); a solid neighbour
+// takes eps(x).
+template <class R, int Q = 1>
+__device__ inline void eps_grad_acc(const R *__restrict__ E, const Nbr &b, R e0, R &gx, R &gy, R &gz)
+{
+    const uint32_t o = shifted<Q, 1>(b);
+    bool solid = false;
+    if (cx(Q) < 0) solid = solid || b.sxm;
+    if (cx(Q) > 0) solid = solid || b.sxp;
+    if (cy(Q) < 0) solid = solid || b.sym;
+    if (cy(Q) > 0) solid = solid || b.syp;
+    if (cz(Q) < 0) solid = solid || b.szm;
+    if (cz(Q) > 0) solid = solid || b.szp;
+    const R e = solid ? e0 : E[o];
+    const R we = weight<R>(Q) * e;
+    if (cx(Q)) gx += cx(Q) > 0 ? we : -we;
+    if (cy(Q)) gy += cy(Q) > 0 ? we : -we;
+    if (cz(Q)) gz += cz(Q) > 0 ? we : -we;
+    if constexpr (Q + 1 < NQ) eps_grad_acc<R, Q + 1>(E, b, e0, gx, gy, gz);
+}
+
+// colour gradient, Eq. macros: F = sum_{q != 0} rho_1(x + v_q) v_q
+template <class R, int Q = 1>
+__device__ inline void colour_acc(const R *__restrict__ C1, const Nbr &b, R &Fx, R &Fy, R &Fz)
+{
+    const R r = C1[shifted<Q, 1>(b)];
+    if (cx(Q)) Fx += cx(Q) > 0 ? r : -r;
+    if (cy(Q)) Fy += cy(Q) > 0 ? r : -r;
+    if (cz(Q)) Fz += cz(Q) > 0 ? r : -r;
+    if constexpr (Q + 1 < NQ) colour_acc<R, Q + 1>(C1, b, Fx, Fy, Fz);
+}
+
+template <class R> struct Newton { static constexpr int iters = 4; };
+template <> struct Newton<double> { static constexpr int iters = 6; };
+
+// |V'| of the implicit velocity V'_a = W_a / (lam_a + mu_a |V'|): Newton on
+// phi(s) = s - sqrt(sum_a W_a^2 / (lam_a + mu_a s)^2) from the Darcy-only
+// value, an upper bound of the root.
+template <class R>
+__device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3])
+{
+    R s = sqrt((W[0] / lam[0]) * (W[0] / lam[0]) + (W[1] / lam[1]) * (W[1] / lam[1]) +
+               (W[2] / lam[2]) * (W[2] / lam[2]));
+    if (s > R(0)) {
+#pragma unroll
+        for (int it = 0; it < Newton<R>::iters; ++it) {
+            R R2 = 0, dR = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R d = lam[a] + mu[a] * s;
+                const R t = W[a] / d;
+                R2 += t * t;
+                dR += t * t * mu[a] / d;
+            }
+            const R Rn = sqrt(R2);
+            const R phi = s - Rn;
+            const R dphi = R(1) + (Rn > R(0) ? dR / Rn : R(0));
+            s = s - phi / dphi;
+            s = s > R(0) ? s : R(0);
+        }
+    }
+    return s;
+}
+
+// Moments after streaming; populations in deviation form.
+template <class R, int Q = 0>
+__device__ inline void moments_acc(const R *d, R &drho, R &jx, R &jy, R &jz)
+{
+    const R v = d[Q];
+    drho += v;
+    if (cx(Q)) jx += cx(Q) > 0 ? v : -v;
+    if (cy(Q)) jy += cy(Q) > 0 ? v : -v;
+    if (cz(Q)) jz += cz(Q) > 0 ? v : -v;
+    if constexpr (Q + 1 < NQ) moments_acc<R, Q + 1>(d, drho, jx, jy, jz);
+}
+
+// Everything a collision needs about one fluid cell.
+template <class R>
+struct CellState {
+    R drho, rho, u[3], Fx[3], C, tau, omega, eps;
+    R F[3], Fn;           // colour gradient and its norm (two-fluid)
+};
+
+// BGK collision with equilibria of Eqs. equilc1/2 and forcing of Eq.
+// coeffforce1 (weight w_q rho), in deviation form; writes post-collision
+// deviations into d.
+template <class R, int Q = 0>
+__device__ inline void collide_f(R *d, const CellState<R> &c, R st, R iFn, R ie, R uu, R uF, R pre)
+{
+    constexpr R w = weight<R>(Q);
+    const R cu = R(cx(Q)) * c.u[0] + R(cy(Q)) * c.u[1] + R(cz(Q)) * c.u[2];
+    const R cF = R(cx(Q)) * c.Fx[0] + R(cy(Q)) * c.Fx[1] + R(cz(Q)) * c.Fx[2];
+    R eqv, T, stq;
+    if constexpr (Q == 0) {
+        eqv = R(-1.5) * ie * uu;
+        T = pre * (R(-3) * ie * uF);
+        stq = st * c.Fn;
+    } else {
+        eqv = R(3) * cu + R(4.5) * ie * cu * cu - R(1.5) * ie * uu;
+        T = pre * (R(3) * cF + R(9) * ie * cu * cF - R(3) * ie * uF);
+        const R cG = R(cx(Q)) * c.F[0] + R(cy(Q)) * c.F[1] + R(cz(Q)) * c.F[2];
+        stq = st * (cG * cG * iFn - c.Fn);
+    }
+    const R feq = w * c.drho + w * c.rho * eqv + w * stq;
+    d[Q] = d[Q] - c.omega * (d[Q] - feq) + w * c.rho * T;
+    if constexpr (Q + 1 < NQ) collide_f<R, Q + 1>(d, c, st, iFn, ie, uu, uF, pre);
+}
+
+// Solute BGK (Eqs. equild, boltzeqD): h~ = h - omega_D (h - w eps C (1 + 3 v.V*)).
+template <class R, int Q = 0>
+__device__ inline void collide_h(R *h, R epsC, const R vs[3], R omd)
+{
+    constexpr R w = weight<R>(Q);
+    R heq;
+    if constexpr (Q == 0) {
+        heq = w * epsC;
+    } else {
+        const R cv = R(cx(Q)) * vs[0] + R(cy(Q)) * vs[1] + R(cz(Q)) * vs[2];
+        heq = w * epsC * (R(1) + R(3) * cv);
+    }
+    h[Q] = h[Q] - omd * (h[Q] - heq);
+    if constexpr (Q + 1 < NQ) collide_h<R, Q + 1>(h, epsC, vs, omd);
+}
+
+// Two-fluid recolouring: g~ = C f~ + beta C (1 - C) rho w cos(v, F).
+template <class R, int Q = 0>
+__device__ inline void recolour(R *g, const R *d, const CellState<R> &c, R rec, R iFn)
+{
+    constexpr R w = weight<R>(Q);
+    const R ft = w + d[Q];
+    if constexpr (Q == 0) {
+        g[Q] = c.C * ft;
+    } else {
+        constexpr R inv_len = speed2(Q) == 1 ? R(1) : R(0.70710678118654752440);
+        const R cG = R(cx(Q)) * c.F[0] + R(cy(Q)) * c.F[1] + R(cz(Q)) * c.F[2];
+        g[Q] = c.C * ft + rec * w * cG * inv_len * iFn;
+    }
+    if constexpr (Q + 1 < NQ) recolour<R, Q + 1>(g, d, c, rec, iFn);
+}
+
+template <class S, int Q = 0>
+__device__ inline void store_all(S *__restrict__ P, size_t n, uint32_t idx, const typename Codec<S>::R *v)
+{
+    Codec<S>::store(P + size_t(Q) * n + idx, v[Q]);
+    if constexpr (Q + 1 < NQ) store_all<S, Q + 1>(P, n, idx, v);
+}
+
+// Porous velocity and force (Eqs. forcement, expandV, expandVsub with eps on
+// G, diagonal K, optional Forchheimer drag).
+template <class R>
+__device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R nu, const R V[3], R u[3], R Fx[3])
+{
+    const R G[3] = {R(L->G[0]), R(L->G[1]), R(L->G[2])};
+    R W[3], lam[3], mu[3], sk[3];
+    R Feps = R(0);
+    if (L->forch) Feps = R(1.75) / sqrt(R(150) * eps * eps * eps);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        W[a] = V[a] + R(0.5) * eps * G[a];
+        lam[a] = R(1) + R(0.5) * eps * nu * kinv[a];
+        sk[a] = sqrt(kinv[a]);
+        mu[a] = R(0.5) * eps * Feps * sk[a];
+    }
+    R s;
+    if (L->forch) {
+        s = solve_speed<R>(W, lam, mu);
+    } else {
+        s = R(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = W[a] / (lam[a] + mu[a] * s);
+    const R sp = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        Fx[a] = eps * G[a] - eps * nu * kinv[a] * u[a] - eps * Feps * sp * sk[a] * u[a];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reduction of the diagnostic partial sums: wave64 butterfly,
+// then the four waves in a fixed order.  Deterministic.
+__device__ inline void block_reduce_store(double v[NPART], double *out)
+{
+    __shared__ double red[BLOCK / 64][NPART];
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double y = __shfl_xor(x, o, 64);
+            x = (k == 7) ? fmax(x, y) : x + y;
+        }
+        v[k] = x;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) red[wv][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < NPART) {
+        const int k = threadIdx.x;
+        double acc = red[0][k];
+        for (int w = 1; w < BLOCK / 64; ++w) acc = (k == 7) ? fmax(acc, red[w][k]) : acc + red[w][k];
+        out[k] = acc;
+    }
+}
+
+// per-cell contribution: {rho, rho u (3), eps C | rho_1 | 0, |u - u_prev|^2,
+// |u|^2, |u| (max), non-finite}
+template <class R>
+__device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R s4, const R up[3])
+{
+    const bool fin = isfinite(rho) && isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(C);
+    // a non-finite cell only counts as such (selects, no branch)
+    const double r = fin ? double(rho) : 0.0;
+    const double ux = fin ? double(u[0]) : 0.0, uy = fin ? double(u[1]) : 0.0, uz = fin ? double(u[2]) : 0.0;
+    const double px = fin ? double(up[0]) : 0.0, py = fin ? double(up[1]) : 0.0, pz = fin ? double(up[2]) : 0.0;
+    v[0] = r;
+    v[1] = r * ux;
+    v[2] = r * uy;
+    v[3] = r * uz;
+    v[4] = fin ? double(s4) : 0.0;
+    const double dx = ux - px, dy = uy - py, dz = uz - pz;
+    v[5] = dx * dx + dy * dy + dz * dz;
+    v[6] = ux * ux + uy * uy + uz * uz;
+    v[7] = sqrt(v[6]);
+    v[8] = fin ? 0.0 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// The step kernel: pull-stream both lattices, moments, viscosity, porous
+// force, (colour gradient), collide, write the other copy.
+template <int PHYS, class S>
+__global__ __launch_bounds__(BLOCK) void k_step(const BatchArgs a)
+{
+    using R = typename Codec<S>::R;
+    const int gb = xcd_remap(blockIdx.x, a.total_blocks);
+    const int l = find_lattice(a, gb);
+    const LatDev *__restrict__ L = a.lat[l];
+    const int lb = gb - a.blk_start[l];
+    const int flags = a.flags[l];
+    const int src = flags & 1;
+    const bool mom = (flags & 2) != 0;
+    const R nuc = R(a.nuc[l]);
+
+    const uint32_t ncell = L->ncell;
+    const size_t n = ncell;
+    const uint32_t idx = uint32_t(lb) * BLOCK + threadIdx.x;
+    const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+
+    // moments kept for the diagnostics of this step
+    bool has = false;
+    R m_rho = 0, m_C = 0, m_s4 = 0, m_u[3] = {0, 0, 0}, m_up[3] = {0, 0, 0};
+    int type = CELL_SOLID;
+    int x = 0, y = 0, z = 0, face = -1;
+    if (idx < ncell) {
+        z = idx / nxy;
+        const uint32_t r = idx - uint32_t(z) * nxy;
+        y = r / nx;
+        x = r - uint32_t(y) * nx;
+        type = cell_type(L, x, y, z, face);
+    }
+    if (type == CELL_FLUID) {
+        const Nbr b = neighbours(L, x, y, z);
+        R d[NQ];
+        pull_all<S>(static_cast<const S *>(L->f[src]), n, idx, b, d);
+        R hq[NQ];
+        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(static_cast<const S *>(L->h[src]), n, idx, b, hq);
+
+        CellState<R> c;
+        R jx = 0, jy = 0, jz = 0;
+        c.drho = 0;
+        moments_acc<R>(d, c.drho, jx, jy, jz);
+        c.rho = R(1) + c.drho;
+        const R irho = R(1) / c.rho;
+        const R V[3] = {jx * irho, jy * irho, jz * irho};
+
+        c.eps = L->uniform_eps ? R(L->eps_u) : static_cast<const R *>(L->eps)[idx];
+        R kinv[3];
+        if (L->uniform_kinv) {
+            kinv[0] = R(L->kinv_u[0]);
+            kinv[1] = R(L->kinv_u[1]);
+            kinv[2] = R(L->kinv_u[2]);
+        } else {
+            const R *K = static_cast<const R *>(L->kinv);
+            kinv[0] = K[idx];
+            kinv[1] = K[n + idx];
+            kinv[2] = K[2 * n + idx];
+        }
+        const R ie = R(1) / c.eps;
+
+        R sh = 0, rho1 = 0;
+        c.C = 0;
+        if constexpr (PHYS == PH_MISCIBLE) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sh += hq[q];
+            c.C = sh * ie;
+        } else if constexpr (PHYS == PH_IMMISCIBLE) {
+            rho1 = static_cast<const R *>(L->rho1)[idx];
+            c.C = rho1 * irho;
+        }
+
+        R nu;
+        if constexpr (PHYS == PH_IMMISCIBLE) {
+            nu = c.C * R(L->nu1) + (R(1) - c.C) * R(L->nu2);
+        } else if constexpr (PHYS == PH_MISCIBLE) {
+            nu = nuc * exp(R(L->k1) * c.C + R(L->k0));
+        } else {
+            nu = nuc * exp(R(L->k0));
+        }
+        c.tau = R(0.5) + R(3) * nu;
+        c.omega = R(1) / c.tau;
+
+        porous_force<R>(L, c.eps, kinv, nu, V, c.u, c.Fx);
+
+        c.F[0] = c.F[1] = c.F[2] = R(0);
+        c.Fn = R(0);
+        if constexpr (PHYS == PH_IMMISCIBLE) {
+            colour_acc<R>(static_cast<const R *>(L->rho1), b, c.F[0], c.F[1], c.F[2]);
+            c.Fn = sqrt(c.F[0] * c.F[0] + c.F[1] * c.F[1] + c.F[2] * c.F[2]);
+        }
+        const R iFn = c.Fn > R(0) ? R(1) / c.Fn : R(0);
+        const R st = c.Fn > R(0) ? R(L->A) * c.eps * c.tau : R(0);
+        const R uu = c.u[0] * c.u[0] + c.u[1] * c.u[1] + c.u[2] * c.u[2];
+        const R uF = c.u[0] * c.Fx[0] + c.u[1] * c.Fx[1] + c.u[2] * c.Fx[2];
+        const R pre = R(1) - R(0.5) * c.omega;
+        collide_f<R>(d, c, st, iFn, ie, uu, uF, pre);
+
+        const int dst = src ^ 1;
+        if constexpr (PHYS == PH_MISCIBLE) {
+            R vs[3] = {c.u[0], c.u[1], c.u[2]};
+            if (L->eps_grad && !L->uniform_eps) {
+                R gx = 0, gy = 0, gz = 0;
+                eps_grad_acc<R>(static_cast<const R *>(L->eps), b, c.eps, gx, gy, gz);
+                const R k = R(3) * R(L->D) * ie;
+                vs[0] += k * gx;
+                vs[1] += k * gy;
+                vs[2] += k * gz;
+            }
+            collide_h<R>(hq, sh, vs, R(1) / R(L->tau_d));
+            store_all<S>(static_cast<S *>(L->h[dst]), n, idx, hq);
+        } else if constexpr (PHYS == PH_IMMISCIBLE) {
+            R g[NQ];
+            const R rec = c.Fn > R(0) ? R(L->beta) * c.C * (R(1) - c.C) * c.rho : R(0);
+            recolour<R>(g, d, c, rec, iFn);
+            store_all<S>(static_cast<S *>(L->h[dst]), n, idx, g);
+        }
+        store_all<S>(static_cast<S *>(L->f[dst]), n, idx, d);
+
+        if (mom) {
+            R *M = static_cast<R *>(L->mom);
+            const R up[3] = {M[n + idx], M[2 * n + idx], M[3 * n + idx]};
+            M[idx] = c.rho;
+            M[n + idx] = c.u[0];
+            M[2 * n + idx] = c.u[1];
+            M[3 * n + idx] = c.u[2];
+            M[4 * n + idx] = c.C;
+            has = true;
+            m_rho = c.rho;
+            m_C = c.C;
+            m_s4 = PHYS == PH_MISCIBLE ? sh : (PHYS == PH_IMMISCIBLE ? rho1 : R(0));
+            for (int a = 0; a < 3; ++a) {
+                m_u[a] = c.u[a];
+                m_up[a] = up[a];
+            }
+        }
+    }
+    if (mom) {
+        double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (has) diag_contrib<R>(part, m_rho, m_u, m_C, m_s4, m_up);
+        block_reduce_store(part, L->partials + size_t(lb) * NPART);
+    }
+}
+
+// Two-fluid, first pass of a step: the colour field rho_1 of the step being
+// computed (fluid cells: sum of the streamed g; reservoir cells: C_bc rho_bc;
+// solid cells: the wall colour (1 + cos theta)/2), which the step kernel
+// reads at the 18 neighbours for the colour gradient.
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
+{
+    using R = typename Codec<S>::R;
+    const int gb = xcd_remap(blockIdx.x, a.total_blocks);
+    const int l = find_lattice(a, gb);
+    const LatDev *__restrict__ L = a.lat[l];
+    const int lb = gb - a.blk_start[l];
+    const int src = a.flags[l] & 1;
+    const uint32_t ncell = L->ncell;
+    const uint32_t idx = uint32_t(lb) * BLOCK + threadIdx.x;
+    if (idx >= ncell) return;
+    const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+    const int z = idx / nxy;
+    const uint32_t r = idx - uint32_t(z) * nxy;
+    const int y = r / nx;
+    const int x = r - uint32_t(y) * nx;
+    int face;
+    const int type = cell_type(L, x, y, z, face);
+    R v;
+    if (type == CELL_SOLID) {
+        v = R(L->face_cw[face]);
+    } else if (type == CELL_RES) {
+        v = R(L->face_conc[face]) * R(L->face_rho[face]);
+    } else {
+        const Nbr b = neighbours(L, x, y, z);
+        R g[NQ];
+        pull_all<S>(static_cast<const S *>(L->h[src]), ncell, idx, b, g);
+        v = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v += g[q];
+    }
+    static_cast<R *>(L->rho1)[idx] = v;
+}
+
+// Second stage of the diagnostics: one block per lattice sums the per-block
+// partials in a fixed order.
+__global__ __launch_bounds__(BLOCK) void k_diag_final(const BatchArgs a)
+{
+    const int l = blockIdx.x;
+    const LatDev *__restrict__ L = a.lat[l];
+    double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int bk = threadIdx.x; bk < L->nblocks; bk += BLOCK) {
+        const double *p = L->partials + size_t(bk) * NPART;
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) v[k] = (k == 7) ? fmax(v[k], p[k]) : v[k] + p[k];
+    }
+    __shared__ double out[NPART];
+    block_reduce_store(v, out);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *D = L->diag;
+        for (int k = 0; k < 5; ++k) D[k] = out[k];
+        D[5] = out[6] > 0.0 ? out[5] / out[6] : 0.0;
+        D[6] = out[7];
+        D[7] = out[8];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+
+template <class R>
+struct InitArgs {
+    const LatDev *L;
+    const R *rho0, *vel0, *c0;   // NULL: uniform defaults 1, 0, 0
+    double nuc0;                 // nu0 * min(a0 + a1, cap): time factor at t = 0
+};
+
+template <class R>
+__device__ inline bool bad(R v) { return !isfinite(v); }
+
+// colour field of the initial state (two-fluid): C0 rho0 in fluid cells.
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_init_colour(const InitArgs<R> ia)
+{
+    const LatDev *L = ia.L;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= uint32_t(L->ncell)) return;
+    const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+    const int z = idx / nxy;
+    const uint32_t r = idx - uint32_t(z) * nxy;
+    const int y = r / nx, x = r - uint32_t(y) * nx;
+    int face;
+    const int type = cell_type(L, x, y, z, face);
+    R v;
+    if (type == CELL_SOLID) v = R(L->face_cw[face]);
+    else if (type == CELL_RES) v = R(L->face_conc[face]) * R(L->face_rho[face]);
+    else v = (ia.c0 ? ia.c0[idx] : R(0)) * (ia.rho0 ? ia.rho0[idx] : R(1));
+    static_cast<R *>(L->rho1)[idx] = v;
+}
+
+// initial populations (flowchart: f = f^eq, h = h^eq from the fields), the
+// fixed reservoir states, and the moments of step 0; validates the fields.
+template <int PHYS, class S>
+__global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>::R> ia)
+{
+    using R = typename Codec<S>::R;
+    const LatDev *L = ia.L;
+    const uint32_t ncell = L->ncell;
+    const size_t n = ncell;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= ncell) return;
+    const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+    const int z = idx / nxy;
+    const uint32_t r = idx - uint32_t(z) * nxy;
+    const int y = r / nx, x = r - uint32_t(y) * nx;
+    int face;
+    const int type = cell_type(L, x, y, z, face);
+
+    const R eps = L->uniform_eps ? R(L->eps_u) : static_cast<const R *>(L->eps)[idx];
+    R kinv[3];
+    for (int a = 0; a < 3; ++a)
+        kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : static_cast<const R *>(L->kinv)[a * n + idx];
+    const R rho0 = ia.rho0 ? ia.rho0[idx] : R(1);
+    R u0[3];
+    for (int a = 0; a < 3; ++a) u0[a] = ia.vel0 ? ia.vel0[a * n + idx] : R(0);
+    const R c0 = ia.c0 ? ia.c0[idx] : R(0);
+    if (!(eps > R(0) && eps <= R(1)) || bad(kinv[0]) || bad(kinv[1]) || bad(kinv[2]) ||
+        kinv[0] < R(0) || kinv[1] < R(0) || kinv[2] < R(0) || !(rho0 > R(0)) || bad(rho0) ||
+        bad(u0[0]) || bad(u0[1]) || bad(u0[2]) || bad(c0)) {
+        *L->err = 1;
+    }
+
+    R d[NQ], hq[NQ];
+    R mrho = 0, mu[3] = {0, 0, 0}, mC = 0;
+    if (type == CELL_SOLID) {
+        for (int q = 0; q < NQ; ++q) d[q] = hq[q] = R(0);
+    } else if (type == CELL_RES) {
+        const R rb = R(L->face_rho[face]), cb = R(L->face_conc[face]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const R w = weight<R>(q);
+            d[q] = w * (rb - R(1));
+            hq[q] = PHYS == PH_MISCIBLE ? w * eps * cb : (PHYS == PH_IMMISCIBLE ? cb * w * rb : R(0));
+        }
+        mrho = rb;
+        mC = PHYS == PH_SINGLE ? R(0) : cb;
+    } else {
+        const Nbr b = neighbours(L, x, y, z);
+        CellState<R> c;
+        c.drho = rho0 - R(1);
+        c.rho = rho0;
+        c.eps = eps;
+        c.C = PHYS == PH_SINGLE ? R(0) : c0;
+        R nu;
+        if constexpr (PHYS == PH_IMMISCIBLE) nu = c.C * R(L->nu1) + (R(1) - c.C) * R(L->nu2);
+        else nu = R(ia.nuc0) * exp(R(L->k1) * (PHYS == PH_MISCIBLE ? c.C : R(0)) + R(L->k0));
+        c.tau = R(0.5) + R(3) * nu;
+        c.omega = R(1);           // d := f^eq below
+        for (int a = 0; a < 3; ++a) {
+            c.u[a] = u0[a];
+            c.Fx[a] = R(0);
+            c.F[a] = R(0);
+        }
+        c.Fn = R(0);
+        if constexpr (PHYS == PH_IMMISCIBLE) {
+            colour_acc<R>(static_cast<const R *>(L->rho1), b, c.F[0], c.F[1], c.F[2]);
+            c.Fn = sqrt(c.F[0] * c.F[0] + c.F[1] * c.F[1] + c.F[2] * c.F[2]);
+        }
+        const R iFn = c.Fn > R(0) ? R(1) / c.Fn : R(0);
+        const R st = c.Fn > R(0) ? R(L->A) * eps * c.tau : R(0);
+        const R uu = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+        for (int q = 0; q < NQ; ++q) d[q] = R(0);
+        // with omega = 1 and no force the collision returns f^eq exactly
+        collide_f<R>(d, c, st, iFn, R(1) / eps, uu, R(0), R(0));
+        if constexpr (PHYS == PH_MISCIBLE) {
+            R vs[3] = {u0[0], u0[1], u0[2]};
+            if (L->eps_grad && !L->uniform_eps) {
+                R gx = 0, gy = 0, gz = 0;
+                eps_grad_acc<R>(static_cast<const R *>(L->eps), b, eps, gx, gy, gz);
+                const R k = R(3) * R(L->D) / eps;
+                vs[0] += k * gx;
+                vs[1] += k * gy;
+                vs[2] += k * gz;
+            }
+            for (int q = 0; q < NQ; ++q) hq[q] = R(0);
+            collide_h<R>(hq, eps * c0, vs, R(1));
+        } else if constexpr (PHYS == PH_IMMISCIBLE) {
+            recolour<R>(hq, d, c, R(0), R(0));
+        } else {
+            for (int q = 0; q < NQ; ++q) hq[q] = R(0);
+        }
+        mrho = rho0;
+        mu[0] = u0[0];
+        mu[1] = u0[1];
+        mu[2] = u0[2];
+        mC = c.C;
+    }
+    for (int cpy = 0; cpy < 2; ++cpy) {
+        store_all<S>(static_cast<S *>(L->f[cpy]), n, idx, d);
+        if constexpr (PHYS != PH_SINGLE) store_all<S>(static_cast<S *>(L->h[cpy]), n, idx, hq);
+    }
+    R *M = static_cast<R *>(L->mom);
+    M[idx] = mrho;
+    M[n + idx] = mu[0];
+    M[2 * n + idx] = mu[1];
+    M[3 * n + idx] = mu[2];
+    M[4 * n + idx] = mC;
+}
+
+// diagnostics of the moments buffer (used after set-up: residual 0)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_diag_moments(const LatDev *L)
+{
+    const uint32_t ncell = L->ncell;
+    const size_t n = ncell;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (idx < ncell) {
+        const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+        const int z = idx / nxy;
+        const uint32_t r = idx - uint32_t(z) * nxy;
+        const int y = r / nx, x = r - uint32_t(y) * nx;
+        int face;
+        if (cell_type(L, x, y, z, face) == CELL_FLUID) {
+            const R *M = static_cast<const R *>(L->mom);
+            const R u[3] = {M[n + idx], M[2 * n + idx], M[3 * n + idx]};
+            const R rho = M[idx], C = M[4 * n + idx];
+            R s4 = 0;
+            if (L->physics == PH_MISCIBLE)
+                s4 = (L->uniform_eps ? R(L->eps_u) : static_cast<const R *>(L->eps)[idx]) * C;
+            else if (L->physics == PH_IMMISCIBLE)
+                s4 = static_cast<const R *>(L->rho1)[idx];
+            diag_contrib<R>(part, rho, u, C, s4, u);
+        }
+    }
+    block_reduce_store(part, L->partials + size_t(blockIdx.x) * NPART);
+}
+
+// decode the current populations of one lattice to the compute type
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, int src, typename Codec<S>::R *dst)
+{
+    const uint32_t ncell = L->ncell;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= ncell) return;
+    const S *P = static_cast<const S *>(which == 0 ? L->f[src] : L->h[src]);
+    for (int q = 0; q < NQ; ++q) dst[size_t(q) * ncell + idx] = Codec<S>::load(P + size_t(q) * ncell + idx);
+}
+
+}  // namespace plbm

@@ -1,0 +1,507 @@
+// lbm.hip -- host side of the C ABI declared in include/lbm.h: argument
+// validation, workspace layout, kernel launch sequencing and diagnostics
+// read-back.  The library never allocates device memory; every buffer lives
+// in the caller's workspace.
+#include "lbm.h"
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+
+#include "kernels.hpp"
+
+using namespace plbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t storage_bytes(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    default: return 2;
+    }
+}
+
+size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+struct Layout {
+    size_t lat, err, diag, partials, eps, kinv, mom, rho1, f0, f1, h0, h1, total;
+};
+
+bool is_fin(double v) { return isfinite(v) != 0; }
+
+// Validation of a description; no GPU call.
+bool valid_desc(const lbm_desc *d)
+{
+    if (!d) return false;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
+    const long long ncell = (long long)d->nx * d->ny * d->nz;
+    if (ncell > (1LL << 31) - BLOCK) return false;
+    if (d->physics < LBM_SINGLE || d->physics > LBM_IMMISCIBLE) return false;
+    if (d->storage < LBM_F64 || d->storage > LBM_F16_DEV) return false;
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int a = 0; a < 3; ++a) {
+        const int k0 = d->face[2 * a].kind, k1 = d->face[2 * a + 1].kind;
+        for (int k : {k0, k1})
+            if (k < LBM_FACE_PERIODIC || k > LBM_FACE_RESERVOIR) return false;
+        if ((k0 == LBM_FACE_PERIODIC) != (k1 == LBM_FACE_PERIODIC)) return false;
+        if (k0 != LBM_FACE_PERIODIC && n[a] < 3) return false;
+    }
+    for (int f = 0; f < 6; ++f) {
+        const lbm_face &F = d->face[f];
+        if (F.kind == LBM_FACE_RESERVOIR && !(F.rho > 0.0 && is_fin(F.rho) && is_fin(F.conc))) return false;
+        if (F.kind == LBM_FACE_WALL && !is_fin(F.contact_angle_deg)) return false;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!is_fin(d->G[a])) return false;
+    if (d->physics == LBM_IMMISCIBLE) {
+        if (!(d->tau1 > 0.5) || !(d->tau2 > 0.5) || !is_fin(d->tau1) || !is_fin(d->tau2)) return false;
+        if (!(d->A >= 0.0) || !is_fin(d->A)) return false;
+        if (!(d->beta >= 0.0 && d->beta <= 1.0)) return false;
+    } else {
+        if (!(d->nu0 > 0.0) || !is_fin(d->nu0)) return false;
+        if (!(d->a0 >= 0.0) || !(d->a1 >= 0.0) || !(d->a0 + d->a1 > 0.0)) return false;
+        if (!is_fin(d->a0) || !is_fin(d->a1) || !is_fin(d->alpha) || !is_fin(d->k1) || !is_fin(d->k0)) return false;
+        if (!(d->cap > 0.0)) return false;
+        if (d->A != 0.0) return false;  // surface tension belongs to the two-fluid model
+    }
+    if (d->physics == LBM_MISCIBLE && (!(d->tau_d > 0.5) || !is_fin(d->tau_d))) return false;
+    if (d->diag_every < 0) return false;
+    return true;
+}
+
+Layout layout(const lbm_desc *d)
+{
+    Layout L;
+    const size_t n = (size_t)d->nx * d->ny * d->nz;
+    const size_t nb = (n + BLOCK - 1) / BLOCK;
+    const size_t sb = storage_bytes(d->storage), rb = real_bytes(d->storage);
+    size_t o = 0;
+    L.lat = o;       o = align_up(o + sizeof(LatDev));
+    L.err = o;       o = align_up(o + sizeof(int));
+    L.diag = o;      o = align_up(o + 8 * sizeof(double));
+    L.partials = o;  o = align_up(o + nb * NPART * sizeof(double));
+    L.eps = o;       o = align_up(o + n * rb);
+    L.kinv = o;      o = align_up(o + 3 * n * rb);
+    L.mom = o;       o = align_up(o + 5 * n * rb);
+    L.rho1 = o;      if (d->physics == LBM_IMMISCIBLE) o = align_up(o + n * rb);
+    L.f0 = o;        o = align_up(o + NQ * n * sb);
+    L.f1 = o;        o = align_up(o + NQ * n * sb);
+    L.h0 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * n * sb);
+    L.h1 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * n * sb);
+    L.total = o;
+    return L;
+}
+
+double time_factor(const lbm_desc *d, double t)
+{
+    double tf = d->a0 + d->a1 * exp(d->alpha * t);
+    if (tf > d->cap) tf = d->cap;
+    return tf;
+}
+
+}  // namespace
+
+struct lbm_sim {
+    lbm_desc d;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    Layout lay;
+    LatDev host;        // host copy of the device parameter block
+    LatDev *dev;        // the device parameter block (inside ws)
+    long long steps;    // completed steps
+    int cur;            // copy holding the current state
+    int ready;          // medium set
+    int nblocks;
+    int device;
+};
+
+namespace {
+
+lbm_status dev_err(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+using Launch = void (*)(const BatchArgs &, int blocks, hipStream_t);
+
+template <int P, class S>
+void launch_step(const BatchArgs &a, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step<P, S>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+
+template <class S>
+void launch_colour(const BatchArgs &a, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_colour<S>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+
+template <int P>
+Launch step_for_storage(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return launch_step<P, double>;
+    case LBM_F32: return launch_step<P, float>;
+    case LBM_BF16_DEV: return launch_step<P, bf16_t>;
+    default: return launch_step<P, f16_t>;
+    }
+}
+
+Launch step_launcher(int physics, int storage)
+{
+    switch (physics) {
+    case LBM_SINGLE: return step_for_storage<PH_SINGLE>(storage);
+    case LBM_MISCIBLE: return step_for_storage<PH_MISCIBLE>(storage);
+    default: return step_for_storage<PH_IMMISCIBLE>(storage);
+    }
+}
+
+Launch colour_launcher(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return launch_colour<double>;
+    case LBM_F32: return launch_colour<float>;
+    case LBM_BF16_DEV: return launch_colour<bf16_t>;
+    default: return launch_colour<f16_t>;
+    }
+}
+
+template <int P, class S>
+void launch_init(const lbm_sim *h, const lbm_medium *m, int blocks)
+{
+    using R = typename Codec<S>::R;
+    InitArgs<R> ia;
+    ia.L = h->dev;
+    ia.rho0 = static_cast<const R *>(m->rho0);
+    ia.vel0 = static_cast<const R *>(m->vel0);
+    ia.c0 = static_cast<const R *>(m->c0);
+    ia.nuc0 = h->d.nu0 * time_factor(&h->d, 0.0);
+    if (P == PH_IMMISCIBLE)
+        hipLaunchKernelGGL((k_init_colour<R>), dim3(blocks), dim3(BLOCK), 0, h->stream, ia);
+    hipLaunchKernelGGL((k_init<P, S>), dim3(blocks), dim3(BLOCK), 0, h->stream, ia);
+    hipLaunchKernelGGL((k_diag_moments<R>), dim3(blocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev);
+}
+
+template <int P>
+void init_for_storage(const lbm_sim *h, const lbm_medium *m, int blocks)
+{
+    switch (h->d.storage) {
+    case LBM_F64: launch_init<P, double>(h, m, blocks); break;
+    case LBM_F32: launch_init<P, float>(h, m, blocks); break;
+    case LBM_BF16_DEV: launch_init<P, bf16_t>(h, m, blocks); break;
+    default: launch_init<P, f16_t>(h, m, blocks); break;
+    }
+}
+
+// Is step t (1-based) of this handle a diagnostic step?
+bool diag_step(const lbm_sim *h, long long t, bool last)
+{
+    return last || (h->d.diag_every > 0 && t % h->d.diag_every == 0);
+}
+
+// One batched step for lattices hs[0..n) of the same physics and storage:
+// [colour pass,] step kernel, [diagnostics second stage].
+lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
+{
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n;
+    int total = 0;
+    int ndiag = 0;
+    BatchArgs diag;
+    memset(&diag, 0, sizeof(diag));
+    for (int i = 0; i < n; ++i) {
+        const lbm_sim *h = hs[i];
+        a.blk_start[i] = total;
+        total += h->nblocks;
+        a.lat[i] = h->dev;
+        const long long t = h->steps + 1;
+        const bool dg = diag_step(h, t, last[i]);
+        a.flags[i] = h->cur | (dg ? 2 : 0);
+        a.nuc[i] = h->d.nu0 * time_factor(&h->d, double(t));
+        if (dg) diag.lat[ndiag++] = h->dev;
+    }
+    a.blk_start[n] = total;
+    a.total_blocks = total;
+    const lbm_sim *h0 = hs[0];
+    if (h0->d.physics == LBM_IMMISCIBLE) colour_launcher(h0->d.storage)(a, total, h0->stream);
+    step_launcher(h0->d.physics, h0->d.storage)(a, total, h0->stream);
+    if (ndiag) {
+        diag.n = ndiag;
+        hipLaunchKernelGGL(k_diag_final, dim3(ndiag), dim3(BLOCK), 0, h0->stream, diag);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return LBM_EDEVICE;
+    for (int i = 0; i < n; ++i) {
+        hs[i]->cur ^= 1;
+        hs[i]->steps += 1;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_desc *d)
+{
+    if (!valid_desc(d)) return 0;
+    return layout(d).total;
+}
+
+lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_t *out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (!valid_desc(d) || !dev_workspace) return LBM_EINVAL;
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN) return LBM_EINVAL;
+    const Layout L = layout(d);
+    if (ws_bytes < L.total) return LBM_ENOMEM;
+    lbm_sim *h = new (std::nothrow) lbm_sim;
+    if (!h) return LBM_ENOMEM;
+    memset(h, 0, sizeof(*h));
+    h->d = *d;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->ws = static_cast<char *>(dev_workspace);
+    h->ws_bytes = ws_bytes;
+    h->lay = L;
+    const size_t n = (size_t)d->nx * d->ny * d->nz;
+    h->nblocks = int((n + BLOCK - 1) / BLOCK);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return LBM_EDEVICE;
+    }
+
+    LatDev &D = h->host;
+    D.nx = d->nx;
+    D.ny = d->ny;
+    D.nz = d->nz;
+    D.ncell = int(n);
+    D.nblocks = h->nblocks;
+    D.physics = d->physics;
+    D.forch = d->forchheimer ? 1 : 0;
+    D.eps_grad = d->eps_gradient ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        D.wall_lo[a] = d->face[2 * a].kind == LBM_FACE_WALL;
+        D.wall_hi[a] = d->face[2 * a + 1].kind == LBM_FACE_WALL;
+        D.res_lo[a] = d->face[2 * a].kind == LBM_FACE_RESERVOIR;
+        D.res_hi[a] = d->face[2 * a + 1].kind == LBM_FACE_RESERVOIR;
+        D.G[a] = d->G[a];
+    }
+    D.k1 = d->k1;
+    D.k0 = d->k0;
+    D.nu1 = (d->tau1 - 0.5) / 3.0;
+    D.nu2 = (d->tau2 - 0.5) / 3.0;
+    D.tau_d = d->tau_d;
+    D.D = (d->tau_d - 0.5) / 3.0;
+    D.A = d->A;
+    D.beta = d->beta;
+    const double pi = 3.14159265358979323846;
+    for (int f = 0; f < 6; ++f) {
+        D.face_rho[f] = d->face[f].rho;
+        D.face_conc[f] = d->face[f].conc;
+        D.face_cw[f] = 0.5 * (1.0 + cos(d->face[f].contact_angle_deg * pi / 180.0));
+    }
+    char *w = h->ws;
+    D.f[0] = w + L.f0;
+    D.f[1] = w + L.f1;
+    D.h[0] = d->physics != LBM_SINGLE ? w + L.h0 : nullptr;
+    D.h[1] = d->physics != LBM_SINGLE ? w + L.h1 : nullptr;
+    D.eps = w + L.eps;
+    D.kinv = w + L.kinv;
+    D.mom = w + L.mom;
+    D.rho1 = d->physics == LBM_IMMISCIBLE ? w + L.rho1 : nullptr;
+    D.partials = reinterpret_cast<double *>(w + L.partials);
+    D.diag = reinterpret_cast<double *>(w + L.diag);
+    D.err = reinterpret_cast<int *>(w + L.err);
+    h->dev = reinterpret_cast<LatDev *>(w + L.lat);
+    *out = h;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
+{
+    if (!h || !m) return LBM_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    const size_t n = (size_t)h->host.ncell;
+    const size_t rb = real_bytes(h->d.storage);
+    LatDev &D = h->host;
+    D.uniform_eps = m->eps ? 0 : 1;
+    D.uniform_kinv = m->kinv ? 0 : 1;
+    D.eps_u = m->eps_uniform;
+    for (int a = 0; a < 3; ++a) D.kinv_u[a] = m->kinv_uniform[a];
+    if (!m->eps && !(m->eps_uniform > 0.0 && m->eps_uniform <= 1.0)) return LBM_EINVAL;
+    if (!m->kinv)
+        for (int a = 0; a < 3; ++a)
+            if (!(m->kinv_uniform[a] >= 0.0) || !is_fin(m->kinv_uniform[a])) return LBM_EINVAL;
+    lbm_status st;
+    if ((st = dev_err(hipMemcpyAsync(h->dev, &D, sizeof(LatDev), hipMemcpyHostToDevice, h->stream)))) return st;
+    static const int zero = 0;
+    if ((st = dev_err(hipMemcpyAsync(D.err, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream)))) return st;
+    if (m->eps && (st = dev_err(hipMemcpyAsync(D.eps, m->eps, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    if (m->kinv && (st = dev_err(hipMemcpyAsync(D.kinv, m->kinv, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    switch (h->d.physics) {
+    case LBM_SINGLE: init_for_storage<PH_SINGLE>(h, m, h->nblocks); break;
+    case LBM_MISCIBLE: init_for_storage<PH_MISCIBLE>(h, m, h->nblocks); break;
+    default: init_for_storage<PH_IMMISCIBLE>(h, m, h->nblocks); break;
+    }
+    BatchArgs diag;
+    memset(&diag, 0, sizeof(diag));
+    diag.n = 1;
+    diag.lat[0] = h->dev;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(BLOCK), 0, h->stream, diag);
+    if ((st = dev_err(hipGetLastError()))) return st;
+    int err = 0;
+    if ((st = dev_err(hipMemcpyAsync(&err, D.err, sizeof(int), hipMemcpyDeviceToHost, h->stream)))) return st;
+    if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
+    h->steps = 0;
+    h->cur = 0;
+    if (err) {
+        h->ready = 0;
+        return LBM_EINVAL;
+    }
+    h->ready = 1;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_t h, int nsteps)
+{
+    if (!h || nsteps < 0) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    for (int s = 0; s < nsteps; ++s) {
+        const bool last = s + 1 == nsteps;
+        lbm_sim *one[1] = {h};
+        const lbm_status st = launch_batch_step(one, &last, 1);
+        if (st) return st;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n)
+{
+    if (!hs || !nsteps || n < 0) return LBM_EINVAL;
+    int maxs = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || nsteps[i] < 0) return LBM_EINVAL;
+        if (!hs[i]->ready) return LBM_ESTATE;
+        if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return LBM_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return LBM_EINVAL;
+        if (nsteps[i] > maxs) maxs = nsteps[i];
+    }
+    if (n == 0) return LBM_OK;
+    if (hipSetDevice(hs[0]->device) != hipSuccess) return LBM_EDEVICE;
+    lbm_sim *grp[MAXB];
+    bool last[MAXB];
+    for (int s = 0; s < maxs; ++s) {
+        // group the lattices still running by (physics, storage)
+        for (int phys = 0; phys < 3; ++phys)
+            for (int stg = 0; stg < 4; ++stg) {
+                int k = 0;
+                for (int i = 0; i < n; ++i) {
+                    lbm_sim *h = hs[i];
+                    if (s >= nsteps[i] || h->d.physics != phys || h->d.storage != stg) continue;
+                    grp[k] = h;
+                    last[k] = s + 1 == nsteps[i];
+                    if (++k == MAXB) {
+                        const lbm_status st = launch_batch_step(grp, last, k);
+                        if (st) return st;
+                        k = 0;
+                    }
+                }
+                if (k) {
+                    const lbm_status st = launch_batch_step(grp, last, k);
+                    if (st) return st;
+                }
+            }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8])
+{
+    if (!h) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    const size_t n = (size_t)h->host.ncell;
+    const size_t rb = real_bytes(h->d.storage);
+    const char *M = static_cast<const char *>(h->host.mom);
+    lbm_status st;
+    if (rho && (st = dev_err(hipMemcpyAsync(rho, M, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    if (vel3 && (st = dev_err(hipMemcpyAsync(vel3, M + n * rb, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    if (conc && (st = dev_err(hipMemcpyAsync(conc, M + 4 * n * rb, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    double dg[8];
+    if ((st = dev_err(hipMemcpyAsync(dg, h->host.diag, sizeof(dg), hipMemcpyDeviceToHost, h->stream)))) return st;
+    if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
+    if (diag) memcpy(diag, dg, sizeof(dg));
+    return dg[7] != 0.0 ? LBM_EUNSTABLE : LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_t h, int lattice, void *dst)
+{
+    if (!h || !dst || lattice < 0 || lattice > 1) return LBM_EINVAL;
+    if (lattice == 1 && h->d.physics == LBM_SINGLE) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    const LatDev *L = h->dev;
+    switch (h->d.storage) {
+    case LBM_F64:
+        hipLaunchKernelGGL(k_export<double>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<double *>(dst));
+        break;
+    case LBM_F32:
+        hipLaunchKernelGGL(k_export<float>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
+        break;
+    case LBM_BF16_DEV:
+        hipLaunchKernelGGL(k_export<bf16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
+        break;
+    default:
+        hipLaunchKernelGGL(k_export<f16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
+        break;
+    }
+    lbm_status st;
+    if ((st = dev_err(hipGetLastError()))) return st;
+    return dev_err(hipStreamSynchronize(h->stream));
+}
+
+long long lbm_steps_done(lbm_t h) { return h ? h->steps : -1; }
+
+lbm_status lbm_destroy(lbm_t h)
+{
+    if (!h) return LBM_EINVAL;
+    delete h;
+    return LBM_OK;
+}
+
+void lbm_lattice(int vel[57], double w[19])
+{
+    for (int q = 0; q < NQ; ++q) {
+        if (vel) {
+            vel[3 * q] = cx(q);
+            vel[3 * q + 1] = cy(q);
+            vel[3 * q + 2] = cz(q);
+        }
+        if (w) w[q] = weight<double>(q);
+    }
+}
+
+const char *lbm_strerror(lbm_status s)
+{
+    switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EDEVICE: return "HIP runtime or kernel launch failure";
+    case LBM_EUNSTABLE: return "non-finite moments (unstable run)";
+    case LBM_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+"""Simulation: one lattice on the GPU, with its workspace in a torch tensor.
+
+Thin convenience layer over the C ABI (binding.py): PyTorch provides the
+device memory and the stream; every step of the update runs in the HIP
+kernels of libporolbm.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import binding as B
+from . import inputs as I
+
+
+def make_desc(p: I.Problem, storage: int = B.LBM_F32, diag_every: int = 0) -> B.lbm_desc:
+    d = B.lbm_desc()
+    d.nx, d.ny, d.nz = (int(v) for v in p.shape)
+    d.physics = int(p.physics)
+    d.storage = int(storage)
+    d.forchheimer = int(bool(p.forchheimer))
+    d.eps_gradient = int(bool(p.eps_grad))
+    d.G = (C.c_double * 3)(*[float(g) for g in p.G])
+    d.nu0, d.a0, d.a1, d.alpha = float(p.nu0), float(p.a0), float(p.a1), float(p.alpha)
+    d.cap, d.k1, d.k0 = float(p.cap), float(p.k1), float(p.k0)
+    d.tau1, d.tau2, d.tau_d = float(p.tau1), float(p.tau2), float(p.tau_d)
+    d.A, d.beta = float(p.A), float(p.beta)
+    for f in range(6):
+        F = p.faces[f]
+        d.face[f].kind = int(F.kind)
+        d.face[f].rho = float(F.rho)
+        d.face[f].conc = float(F.conc)
+        d.face[f].contact_angle_deg = float(F.angle)
+    d.diag_every = int(diag_every)
+    return d
+
+
+def real_dtype(storage: int):
+    import torch
+    return torch.float64 if storage == B.LBM_F64 else torch.float32
+
+
+class Simulation:
+    """One lattice resident on a GPU.
+
+    problem: a seeded `inputs.Problem`; storage: LBM_F64 / F32 / BF16_DEV /
+    F16_DEV (or "f64", "f32", "bf16", "f16"); stream: a torch.cuda.Stream
+    (default: the current stream of the device).
+    """
+
+    def __init__(self, problem: I.Problem, storage=B.LBM_F32, device="cuda:0", stream=None,
+                 diag_every: int = 0, uniform_medium: bool = True):
+        import torch
+        if isinstance(storage, str):
+            storage = B.STORAGE_NAMES[storage]
+        p = problem.fill_defaults()
+        self.problem = p
+        self.storage = storage
+        self.device = torch.device(device)
+        self.dtype = real_dtype(storage)
+        self.desc = make_desc(p, storage, diag_every)
+        nbytes = B.lbm_workspace_bytes(self.desc)
+        if nbytes == 0:
+            raise B.LbmError(B.LBM_EINVAL, "lbm_workspace_bytes")
+        self.nbytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.h = B.lbm_create(self.desc, self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
+        self.shape = tuple(p.shape)
+        self._set_medium(p, uniform_medium)
+
+    # ------------------------------------------------------------------
+    def _dev(self, a):
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device, self.dtype)
+
+    def _set_medium(self, p: I.Problem, uniform_medium: bool):
+        import torch
+        m = B.lbm_medium()
+        keep = []
+        eps_u = bool(uniform_medium and np.all(p.eps == p.eps.flat[0]))
+        kinv_u = bool(uniform_medium and all(np.all(p.kinv[a] == p.kinv[a].flat[0]) for a in range(3)))
+        if eps_u:
+            m.eps = None
+            m.eps_uniform = float(p.eps.flat[0])
+        else:
+            t = self._dev(p.eps)
+            keep.append(t)
+            m.eps = t.data_ptr()
+        if kinv_u:
+            m.kinv = None
+            m.kinv_uniform = (C.c_double * 3)(*[float(p.kinv[a].flat[0]) for a in range(3)])
+        else:
+            t = self._dev(p.kinv)
+            keep.append(t)
+            m.kinv = t.data_ptr()
+        for name, arr in (("rho0", p.rho0), ("vel0", p.vel0), ("c0", p.c0)):
+            t = self._dev(arr)
+            keep.append(t)
+            setattr(m, name, t.data_ptr())
+        with torch.cuda.stream(self.stream):
+            torch.cuda.current_stream(self.device).wait_stream(torch.cuda.default_stream(self.device))
+            B.lbm_set_medium(self.h, m)
+        del keep
+
+    def step(self, n: int = 1) -> "Simulation":
+        B.lbm_step(self.h, n)
+        return self
+
+    @property
+    def steps_done(self) -> int:
+        return B.lbm_steps_done(self.h)
+
+    def moments(self, check: bool = True):
+        """(rho, V' (3,...), C) as device tensors shaped (nz,ny,nx), and the FP64
+        diagnostics as a numpy array of 8."""
+        import torch
+        nx, ny, nz = self.shape
+        rho = torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
+        vel = torch.empty((3, nz, ny, nx), dtype=self.dtype, device=self.device)
+        conc = torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
+        diag = (C.c_double * 8)()
+        B.lbm_moments(self.h, rho.data_ptr(), vel.data_ptr(), conc.data_ptr(), diag, check=check)
+        return rho, vel, conc, np.array(diag[:])
+
+    def diag(self, check: bool = True) -> np.ndarray:
+        diag = (C.c_double * 8)()
+        B.lbm_moments(self.h, 0, 0, 0, diag, check=check)
+        return np.array(diag[:])
+
+    def populations(self, lattice: int = 0):
+        """(19, nz, ny, nx) tensor of the real type: lattice 0 as f - w, 1 as is."""
+        import torch
+        nx, ny, nz = self.shape
+        out = torch.empty((19, nz, ny, nx), dtype=self.dtype, device=self.device)
+        B.lbm_populations(self.h, lattice, out.data_ptr())
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            B.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def step_batch(sims, nsteps):
+    """Advance several simulations (same stream) with batched launches."""
+    B.lbm_step_batch([s.h for s in sims], nsteps)

@@ -1,0 +1,112 @@
+"""The C ABI without a GPU: the library loads, exports every entry point of
+include/lbm.h, sizes workspaces and rejects invalid arguments before any GPU
+call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_0912_4230_amd import binding as B
+from paper_0912_4230_amd import inputs as I
+from paper_0912_4230_amd.sim import make_desc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_function():
+    names = _header_functions()
+    assert set(names) == set(B.EXPORTED), names
+    L = B.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_sizes_match_header():
+    # lbm_face: int + 3 doubles (padded); lbm_desc ends with an int
+    assert C.sizeof(B.lbm_face) == 32
+    assert C.sizeof(B.lbm_medium) == 5 * 8 + 8 + 24
+
+
+def test_lattice_table():
+    vel, w = B.lbm_lattice()
+    assert len(set(vel)) == 19
+    assert abs(sum(w) - 1.0) < 1e-15
+    for q, v in enumerate(vel):
+        s2 = sum(c * c for c in v)
+        assert w[q] == {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}[s2]
+    assert B.lbm_strerror(B.LBM_ENOMEM) == "workspace too small"
+
+
+def _desc(**kw):
+    p = I.poiseuille(shape=(8, 6, 5))
+    d = make_desc(p, B.LBM_F32)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_workspace_size():
+    d = _desc()
+    n = 8 * 6 * 5
+    ws = B.lbm_workspace_bytes(d)
+    assert ws >= 2 * 19 * n * 4 + 4 * n * 4
+    d64 = _desc(storage=B.LBM_F64)
+    assert B.lbm_workspace_bytes(d64) > ws
+    dm = make_desc(I.miscible(shape=(8, 6, 5)), B.LBM_BF16_DEV)
+    dm32 = make_desc(I.miscible(shape=(8, 6, 5)), B.LBM_F32)
+    assert B.lbm_workspace_bytes(dm) < B.lbm_workspace_bytes(dm32)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("physics", 7), ("storage", 9), ("nu0", 0.0), ("nu0", -1.0),
+    ("a0", -1.0), ("cap", 0.0), ("diag_every", -2), ("A", 0.01),
+])
+def test_invalid_descriptions_rejected(field, value):
+    d = _desc(**{field: value})
+    assert B.lbm_workspace_bytes(d) == 0
+    h = C.c_void_p()
+    st = B.lib().lbm_create(C.byref(d), C.c_void_p(1 << 20), C.c_size_t(1 << 30), None, C.byref(h))
+    assert st == B.LBM_EINVAL and not h.value
+
+
+def test_face_rules():
+    d = _desc()
+    d.face[0].kind = B.LBM_FACE_WALL      # -x wall but +x periodic: inconsistent
+    assert B.lbm_workspace_bytes(d) == 0
+    d = _desc()
+    d.face[0].kind = B.LBM_FACE_RESERVOIR
+    d.face[1].kind = B.LBM_FACE_RESERVOIR
+    d.face[0].rho = -1.0
+    assert B.lbm_workspace_bytes(d) == 0
+    d.face[0].rho = 1.1
+    assert B.lbm_workspace_bytes(d) > 0
+    d = make_desc(I.drop(shape=(10, 10, 10), radius=3), B.LBM_F32)
+    d.tau1 = 0.5
+    assert B.lbm_workspace_bytes(d) == 0
+    d.tau1 = 0.7
+    d.beta = 1.5
+    assert B.lbm_workspace_bytes(d) == 0
+
+
+def test_create_checks_before_gpu():
+    d = _desc()
+    need = B.lbm_workspace_bytes(d)
+    h = C.c_void_p()
+    L = B.lib()
+    # workspace too small
+    assert L.lbm_create(C.byref(d), C.c_void_p(1 << 20), C.c_size_t(need - 1), None, C.byref(h)) == B.LBM_ENOMEM
+    # misaligned workspace
+    assert L.lbm_create(C.byref(d), C.c_void_p((1 << 20) + 8), C.c_size_t(need), None, C.byref(h)) == B.LBM_EINVAL
+    # null arguments
+    assert L.lbm_create(None, C.c_void_p(1 << 20), C.c_size_t(need), None, C.byref(h)) == B.LBM_EINVAL
+    assert L.lbm_step(None, 1) == B.LBM_EINVAL
+    assert L.lbm_moments(None, None, None, None, None) == B.LBM_EINVAL
+    assert L.lbm_destroy(None) == B.LBM_EINVAL
+    assert L.lbm_steps_done(None) == -1
