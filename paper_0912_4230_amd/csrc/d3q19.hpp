@@ -4,11 +4,15 @@
 // (+x,-x,+y,-y,+z,-z); 7..18 the twelve face diagonals, each followed by its
 // opposite.  Weights: 1/3 (rest), 1/18 (axes), 1/36 (diagonals), Sec. 2.1 of
 // the paper (sentence after Eq. equilc2).  Components are encoded in bit
-// masks so that every lookup folds to a constant after loop unrolling.
+// masks so that every lookup folds to a constant after unrolling.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// global (HBM) address space: loads and stores through such pointers compile
+// to global_* instructions instead of flat_*
+#define GL __attribute__((address_space(1)))
 
 namespace plbm {
 
@@ -36,6 +40,30 @@ __host__ __device__ constexpr R weight(int q)
 
 // ---------------------------------------------------------------------------
 // storage codecs: Codec<S>::R is the compute type, load/store convert.
+// Populations are streamed: each value is read once, one step after it was
+// written, long after it has left the caches, so both directions use the
+// non-temporal cache policy by default.
+
+#ifndef PLBM_NT_STORE
+#define PLBM_NT_STORE 1
+#endif
+#ifndef PLBM_NT_LOAD
+#define PLBM_NT_LOAD 1
+#endif
+
+template <class T>
+__device__ inline void st(GL T *p, T v)
+{
+    if constexpr (PLBM_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <class T>
+__device__ inline T ld(const GL T *p)
+{
+    if constexpr (PLBM_NT_LOAD) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
 struct bf16_t { uint16_t v; };
 struct f16_t { uint16_t v; };
@@ -44,43 +72,40 @@ template <class S> struct Codec;
 
 template <> struct Codec<double> {
     using R = double;
-    __device__ static R load(const double *p) { return *p; }
-    __device__ static void store(double *p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R load(const GL double *p) { return ld(p); }
+    __device__ static void store(GL double *p, R v) { st(p, v); }
 };
 
 template <> struct Codec<float> {
     using R = float;
-    __device__ static R load(const float *p) { return *p; }
-    __device__ static void store(float *p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R load(const GL float *p) { return ld(p); }
+    __device__ static void store(GL float *p, R v) { st(p, v); }
 };
 
-// bfloat16: the upper half of an IEEE float; encode rounds to nearest even.
+// bfloat16: the upper half of an IEEE float; the hardware conversion
+// (v_cvt_pk_bf16_f32) rounds to nearest even.
 template <> struct Codec<bf16_t> {
     using R = float;
-    __device__ static R load(const bf16_t *p)
+    __device__ static R load(const GL bf16_t *p)
     {
-        return __uint_as_float(uint32_t(p->v) << 16);
+        return __uint_as_float(uint32_t(ld(reinterpret_cast<const GL uint16_t *>(p))) << 16);
     }
-    __device__ static uint16_t encode(float f)
+    __device__ static void store(GL bf16_t *p, R v)
     {
-        uint32_t u = __float_as_uint(f);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return uint16_t(u >> 16);
-    }
-    __device__ static void store(bf16_t *p, R v)
-    {
-        __builtin_nontemporal_store(encode(v), &p->v);
+        st(reinterpret_cast<GL uint16_t *>(p), __builtin_bit_cast(uint16_t, (__bf16)v));
     }
 };
 
 // IEEE binary16: hardware conversion (round to nearest even).
 template <> struct Codec<f16_t> {
     using R = float;
-    __device__ static R load(const f16_t *p) { return float(__builtin_bit_cast(_Float16, p->v)); }
-    __device__ static void store(f16_t *p, R v)
+    __device__ static R load(const GL f16_t *p)
     {
-        __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, _Float16(v)), &p->v);
+        return float(__builtin_bit_cast(_Float16, ld(reinterpret_cast<const GL uint16_t *>(p))));
+    }
+    __device__ static void store(GL f16_t *p, R v)
+    {
+        st(reinterpret_cast<GL uint16_t *>(p), __builtin_bit_cast(uint16_t, _Float16(v)));
     }
 };
 

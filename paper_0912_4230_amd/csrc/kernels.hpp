@@ -9,6 +9,12 @@
 // another.  The hot path is bound by HBM bandwidth, not arithmetic; there is
 // no dense contraction, hence no MFMA.
 //
+// Addressing: every population plane is addressed as a wave-uniform base
+// (scalar registers) plus a 32-bit per-lane byte offset, which maps onto the
+// global_load/global_store "saddr" form; halfway bounce-back is a rare
+// second load under the lane mask.  The collision is refactored into a few
+// fused multiply-adds per direction around per-cell constants.
+//
 // Paper references: Sec. 2.1 (Eqs. macros1, macros, lbe2, coeffforce1,
 // forcement, expandV, expandVsub, equilc1, equilc2), Sec. 2.2 (Eqs. equild,
 // boltzeqD), Sec. 4 (order of the operations of a step), Eq. nuall (local
@@ -22,7 +28,22 @@ namespace plbm {
 enum { PH_SINGLE = 0, PH_MISCIBLE = 1, PH_IMMISCIBLE = 2 };
 enum { CELL_FLUID = 0, CELL_SOLID = 1, CELL_RES = 2 };
 
-constexpr int BLOCK = 256;
+#ifndef PLBM_BLOCK
+#define PLBM_BLOCK 256
+#endif
+#ifndef PLBM_XCD
+#define PLBM_XCD 0
+#endif
+#ifndef PLBM_WPE
+#define PLBM_WPE 0
+#endif
+#if PLBM_WPE > 0
+#define PLBM_STEP_ATTR __launch_bounds__(PLBM_BLOCK) __attribute__((amdgpu_waves_per_eu(PLBM_WPE)))
+#else
+#define PLBM_STEP_ATTR __launch_bounds__(PLBM_BLOCK)
+#endif
+
+constexpr int BLOCK = PLBM_BLOCK;
 constexpr int MAXB = 64;     // lattices per batched launch
 constexpr int NPART = 9;     // diagnostic partial sums per block
 
@@ -61,12 +82,13 @@ struct BatchArgs {
     double nuc[MAXB];
 };
 
-// Hardware dispatch places block b on XCD b mod 8.  Map hardware blocks to
-// logical blocks so that each XCD works through one contiguous range of the
-// lattice: neighbouring cells (halo reads of scalar fields) then share the
-// XCD's L2.
+// Optional mapping of hardware blocks (dispatched round-robin over the 8
+// XCDs) to contiguous logical ranges per XCD.  Off by default: the pull
+// stream reads every population exactly once, so there is no cross-block
+// reuse for the XCD L2s to capture, and measurement favours the identity.
 __device__ inline int xcd_remap(int b, int nb)
 {
+    if (!PLBM_XCD) return b;
     const int X = 8;
     int q = nb / X, r = nb - q * X;
     int xcd = b % X, slot = b / X;
@@ -140,11 +162,11 @@ __device__ inline uint32_t shifted(const Nbr &b)
     return ox + oy + oz;
 }
 
-// is the source x - v_q of the pull solid?
-template <int Q>
-__device__ inline bool source_solid(const Nbr &b)
+// is the cell x + s*v_q solid?
+template <int Q, int SIGN>
+__device__ inline bool shifted_solid(const Nbr &b)
 {
-    constexpr int sx = -cx(Q), sy = -cy(Q), sz = -cz(Q);
+    constexpr int sx = SIGN * cx(Q), sy = SIGN * cy(Q), sz = SIGN * cz(Q);
     bool s = false;
     if (sx < 0) s = s || b.sxm;
     if (sx > 0) s = s || b.sxp;
@@ -155,38 +177,84 @@ __device__ inline bool source_solid(const Nbr &b)
     return s;
 }
 
+template <class T>
+__device__ inline const GL T *plane(const void *base, uint32_t n, int q)
+{
+    return static_cast<const GL T *>((const GL void *)base) + size_t(q) * n;
+}
+
+template <class T>
+__device__ inline GL T *plane_w(void *base, uint32_t n, int q)
+{
+    return static_cast<GL T *>((GL void *)base) + size_t(q) * n;
+}
+
+// element i of a plane: uniform base + zero-extended 32-bit byte offset
+template <class T>
+__device__ inline const GL T *at(const GL T *p, uint32_t i)
+{
+    return reinterpret_cast<const GL T *>(reinterpret_cast<const GL char *>(p) + i * uint32_t(sizeof(T)));
+}
+
+template <class T>
+__device__ inline GL T *at(GL T *p, uint32_t i)
+{
+    return reinterpret_cast<GL T *>(reinterpret_cast<GL char *>(p) + i * uint32_t(sizeof(T)));
+}
+
 // Pull streaming (Eqs. lbe2, boltzeqD): f_q(x) = f~_q(x - v_q), or
 // f~_opp(q)(x) when x - v_q is solid (halfway bounce-back).
-template <class S, int Q>
-__device__ inline typename Codec<S>::R pull_one(const S *__restrict__ P, size_t n, uint32_t idx, const Nbr &b)
+template <class S, bool BB, int Q = 0>
+__device__ inline void pull_each(const void *P, uint32_t n, uint32_t idx, const Nbr &b, typename Codec<S>::R *out)
 {
-    const bool solid = source_solid<Q>(b);
-    const size_t off = solid ? size_t(opp(Q)) * n + idx : size_t(Q) * n + shifted<Q, -1>(b);
-    return Codec<S>::load(P + off);
+    if constexpr (BB && Q != 0) {
+        const bool s = shifted_solid<Q, -1>(b);
+        out[Q] = Codec<S>::load(at(plane<S>(P, n, s ? opp(Q) : Q), s ? idx : shifted<Q, -1>(b)));
+    } else {
+        out[Q] = Codec<S>::load(at(plane<S>(P, n, Q), shifted<Q, -1>(b)));
+    }
+    if constexpr (Q + 1 < NQ) pull_each<S, BB, Q + 1>(P, n, idx, b, out);
+}
+
+// Waves without a wall-adjacent cell (all but a thin layer) take the path
+// without bounce-back selects: uniform plane bases + 32-bit offsets only.
+template <class S>
+__device__ inline void pull_all(const void *P, uint32_t n, uint32_t idx, const Nbr &b, typename Codec<S>::R *out)
+{
+    const bool near_wall = b.sxm || b.sxp || b.sym || b.syp || b.szm || b.szp;
+    if (__builtin_amdgcn_ballot_w64(near_wall) != 0) pull_each<S, true>(P, n, idx, b, out);
+    else pull_each<S, false>(P, n, idx, b, out);
 }
 
 template <class S, int Q = 0>
-__device__ inline void pull_all(const S *__restrict__ P, size_t n, uint32_t idx, const Nbr &b,
-                                typename Codec<S>::R *out)
+__device__ inline void store_all(void *P, uint32_t n, uint32_t idx, const typename Codec<S>::R *v)
 {
-    out[Q] = pull_one<S, Q>(P, n, idx, b);
-    if constexpr (Q + 1 < NQ) pull_all<S, Q + 1>(P, n, idx, b, out);
+    Codec<S>::store(at(plane_w<S>(P, n, Q), idx), v[Q]);
+    if constexpr (Q + 1 < NQ) store_all<S, Q + 1>(P, n, idx, v);
 }
 
-// grad(eps)/eps by 3 sum_q w_q eps(x + v_q) v_q / eps(x); a solid neighbour
-// takes eps(x).
-template <class R, int Q = 1>
-__device__ inline void eps_grad_acc(const R *__restrict__ E, const Nbr &b, R e0, R &gx, R &gy, R &gz)
+template <class R>
+__device__ inline R ldg(const void *base, uint32_t i)
 {
-    const uint32_t o = shifted<Q, 1>(b);
-    bool solid = false;
-    if (cx(Q) < 0) solid = solid || b.sxm;
-    if (cx(Q) > 0) solid = solid || b.sxp;
-    if (cy(Q) < 0) solid = solid || b.sym;
-    if (cy(Q) > 0) solid = solid || b.syp;
-    if (cz(Q) < 0) solid = solid || b.szm;
-    if (cz(Q) > 0) solid = solid || b.szp;
-    const R e = solid ? e0 : E[o];
+    return *at(static_cast<const GL R *>((const GL void *)base), i);
+}
+
+template <class R>
+__device__ inline void stg(void *base, uint32_t i, R v)
+{
+    *at(static_cast<GL R *>((GL void *)base), i) = v;
+}
+
+// reciprocal: the hardware approximation (1 ulp) in FP32, IEEE in FP64
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) { return 1.0 / x; }
+
+// grad(eps) (times eps) by sum_q w_q eps(x + v_q) v_q; a solid neighbour
+// takes eps(x).  The caller scales by 3 / eps(x).
+template <class R, int Q = 1>
+__device__ inline void eps_grad_acc(const void *E, const Nbr &b, R e0, R &gx, R &gy, R &gz)
+{
+    const R e = shifted_solid<Q, 1>(b) ? e0 : ldg<R>(E, shifted<Q, 1>(b));
     const R we = weight<R>(Q) * e;
     if (cx(Q)) gx += cx(Q) > 0 ? we : -we;
     if (cy(Q)) gy += cy(Q) > 0 ? we : -we;
@@ -196,42 +264,44 @@ __device__ inline void eps_grad_acc(const R *__restrict__ E, const Nbr &b, R e0,
 
 // colour gradient, Eq. macros: F = sum_{q != 0} rho_1(x + v_q) v_q
 template <class R, int Q = 1>
-__device__ inline void colour_acc(const R *__restrict__ C1, const Nbr &b, R &Fx, R &Fy, R &Fz)
+__device__ inline void colour_acc(const void *C1, const Nbr &b, R &Fx, R &Fy, R &Fz)
 {
-    const R r = C1[shifted<Q, 1>(b)];
+    const R r = ldg<R>(C1, shifted<Q, 1>(b));
     if (cx(Q)) Fx += cx(Q) > 0 ? r : -r;
     if (cy(Q)) Fy += cy(Q) > 0 ? r : -r;
     if (cz(Q)) Fz += cz(Q) > 0 ? r : -r;
     if constexpr (Q + 1 < NQ) colour_acc<R, Q + 1>(C1, b, Fx, Fy, Fz);
 }
 
-template <class R> struct Newton { static constexpr int iters = 4; };
-template <> struct Newton<double> { static constexpr int iters = 6; };
+template <class R> struct Newton { static constexpr R tol = R(1e-7); };
+template <> struct Newton<double> { static constexpr double tol = 1e-15; };
 
 // |V'| of the implicit velocity V'_a = W_a / (lam_a + mu_a |V'|): Newton on
 // phi(s) = s - sqrt(sum_a W_a^2 / (lam_a + mu_a s)^2) from the Darcy-only
-// value, an upper bound of the root.
+// value, an upper bound of the root; stops when the update is below the
+// working precision (at most 8 iterations).
 template <class R>
-__device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3])
+__device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], const R ilam[3])
 {
-    R s = sqrt((W[0] / lam[0]) * (W[0] / lam[0]) + (W[1] / lam[1]) * (W[1] / lam[1]) +
-               (W[2] / lam[2]) * (W[2] / lam[2]));
+    R s = sqrt((W[0] * ilam[0]) * (W[0] * ilam[0]) + (W[1] * ilam[1]) * (W[1] * ilam[1]) +
+               (W[2] * ilam[2]) * (W[2] * ilam[2]));
     if (s > R(0)) {
-#pragma unroll
-        for (int it = 0; it < Newton<R>::iters; ++it) {
+        for (int it = 0; it < 8; ++it) {
             R R2 = 0, dR = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const R d = lam[a] + mu[a] * s;
-                const R t = W[a] / d;
+                const R id = rcp(lam[a] + mu[a] * s);
+                const R t = W[a] * id;
                 R2 += t * t;
-                dR += t * t * mu[a] / d;
+                dR += t * t * mu[a] * id;
             }
             const R Rn = sqrt(R2);
             const R phi = s - Rn;
             const R dphi = R(1) + (Rn > R(0) ? dR / Rn : R(0));
-            s = s - phi / dphi;
+            const R ds = phi / dphi;
+            s = s - ds;
             s = s > R(0) ? s : R(0);
+            if (!(fabs(ds) > Newton<R>::tol * s)) break;
         }
     }
     return s;
@@ -249,75 +319,112 @@ __device__ inline void moments_acc(const R *d, R &drho, R &jx, R &jy, R &jz)
     if constexpr (Q + 1 < NQ) moments_acc<R, Q + 1>(d, drho, jx, jy, jz);
 }
 
-// Everything a collision needs about one fluid cell.
+template <class R, int Q>
+__device__ inline R cdot(const R v[3])
+{
+    R r = R(0);
+    bool any = false;
+    if constexpr (cx(Q) != 0) { r = cx(Q) > 0 ? v[0] : -v[0]; any = true; }
+    if constexpr (cy(Q) != 0) { r = any ? (cy(Q) > 0 ? r + v[1] : r - v[1]) : (cy(Q) > 0 ? v[1] : -v[1]); any = true; }
+    if constexpr (cz(Q) != 0) { r = any ? (cz(Q) > 0 ? r + v[2] : r - v[2]) : (cz(Q) > 0 ? v[2] : -v[2]); }
+    return r;
+}
+
+// Per-cell constants of the collision.  The BGK update with the equilibria
+// of Eqs. equilc1/2 and the forcing of Eq. coeffforce1 (weight w_q rho),
+//   d' = d - omega (d - f^eq) + w rho T,
+// is rearranged (exactly, in real arithmetic) as
+//   d' = (1 - omega) d + omega w drho + w rho X_q + omega w ST_q,
+//   X_q = 3 (v.a + v.b) + (v.u)(k45 v.a + k9 v.b) - K0,
+// with a = omega u, b = (1 - omega/2) F^ext, k45 = 4.5/eps, k9 = 9/eps,
+// K0 = omega 1.5 |u|^2 / eps + (1 - omega/2) 3 u.F^ext / eps.
 template <class R>
-struct CellState {
-    R drho, rho, u[3], Fx[3], C, tau, omega, eps;
-    R F[3], Fn;           // colour gradient and its norm (two-fluid)
+struct Coll {
+    R om1;                  // 1 - omega
+    R u[3], a[3], b[3];
+    R k45, k9, K0;
+    R base[3], wr[3];       // per weight class: omega w drho (+ surface-tension constant), w rho
+    R F[3], s1[3];          // colour gradient; per class omega w A eps tau / |F|
 };
 
-// BGK collision with equilibria of Eqs. equilc1/2 and forcing of Eq.
-// coeffforce1 (weight w_q rho), in deviation form; writes post-collision
-// deviations into d.
-template <class R, int Q = 0>
-__device__ inline void collide_f(R *d, const CellState<R> &c, R st, R iFn, R ie, R uu, R uF, R pre)
+template <class R>
+__device__ inline Coll<R> make_coll(R drho, R rho, R omega, R ie, const R u[3], const R Fx[3], R st,
+                                    const R F[3], R Fn, R iFn)
 {
-    constexpr R w = weight<R>(Q);
-    const R cu = R(cx(Q)) * c.u[0] + R(cy(Q)) * c.u[1] + R(cz(Q)) * c.u[2];
-    const R cF = R(cx(Q)) * c.Fx[0] + R(cy(Q)) * c.Fx[1] + R(cz(Q)) * c.Fx[2];
-    R eqv, T, stq;
-    if constexpr (Q == 0) {
-        eqv = R(-1.5) * ie * uu;
-        T = pre * (R(-3) * ie * uF);
-        stq = st * c.Fn;
-    } else {
-        eqv = R(3) * cu + R(4.5) * ie * cu * cu - R(1.5) * ie * uu;
-        T = pre * (R(3) * cF + R(9) * ie * cu * cF - R(3) * ie * uF);
-        const R cG = R(cx(Q)) * c.F[0] + R(cy(Q)) * c.F[1] + R(cz(Q)) * c.F[2];
-        stq = st * (cG * cG * iFn - c.Fn);
+    Coll<R> c;
+    const R pre = R(1) - R(0.5) * omega;
+    c.om1 = R(1) - omega;
+    R uu = 0, uF = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c.u[a] = u[a];
+        c.a[a] = omega * u[a];
+        c.b[a] = pre * Fx[a];
+        c.F[a] = F[a];
+        uu += u[a] * u[a];
+        uF += u[a] * Fx[a];
     }
-    const R feq = w * c.drho + w * c.rho * eqv + w * stq;
-    d[Q] = d[Q] - c.omega * (d[Q] - feq) + w * c.rho * T;
-    if constexpr (Q + 1 < NQ) collide_f<R, Q + 1>(d, c, st, iFn, ie, uu, uF, pre);
+    c.k45 = R(4.5) * ie;
+    c.k9 = R(9) * ie;
+    c.K0 = omega * R(1.5) * ie * uu + pre * R(3) * ie * uF;
+    const R w[3] = {weight<R>(0), weight<R>(1), weight<R>(7)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R ost = omega * w[k] * st;          // omega w A eps tau (0 without |F|)
+        c.wr[k] = w[k] * rho;
+        c.base[k] = omega * w[k] * drho + (k == 0 ? ost * Fn : -ost * Fn);
+        c.s1[k] = ost * iFn;
+    }
+    return c;
 }
 
-// Solute BGK (Eqs. equild, boltzeqD): h~ = h - omega_D (h - w eps C (1 + 3 v.V*)).
-template <class R, int Q = 0>
-__device__ inline void collide_h(R *h, R epsC, const R vs[3], R omd)
+template <class R, bool ST, int Q = 0>
+__device__ inline void collide_f(R *d, const Coll<R> &c)
 {
-    constexpr R w = weight<R>(Q);
-    R heq;
+    constexpr int k = Q == 0 ? 0 : (Q <= 6 ? 1 : 2);
+    R v;
     if constexpr (Q == 0) {
-        heq = w * epsC;
+        v = c.base[0] - c.wr[0] * c.K0;
     } else {
-        const R cv = R(cx(Q)) * vs[0] + R(cy(Q)) * vs[1] + R(cz(Q)) * vs[2];
-        heq = w * epsC * (R(1) + R(3) * cv);
+        const R cu = cdot<R, Q>(c.u), ca = cdot<R, Q>(c.a), cb = cdot<R, Q>(c.b);
+        const R X = fma(R(3), ca + cb, fma(cu, fma(c.k45, ca, c.k9 * cb), -c.K0));
+        v = fma(c.wr[k], X, c.base[k]);
+        if constexpr (ST) {
+            const R cG = cdot<R, Q>(c.F);
+            v = fma(c.s1[k] * cG, cG, v);
+        }
     }
-    h[Q] = h[Q] - omd * (h[Q] - heq);
-    if constexpr (Q + 1 < NQ) collide_h<R, Q + 1>(h, epsC, vs, omd);
+    d[Q] = fma(c.om1, d[Q], v);
+    if constexpr (Q + 1 < NQ) collide_f<R, ST, Q + 1>(d, c);
 }
 
-// Two-fluid recolouring: g~ = C f~ + beta C (1 - C) rho w cos(v, F).
+// Solute BGK (Eqs. equild, boltzeqD):
+// h' = (1 - omega_D) h + omega_D w eps C (1 + 3 v.V*).
 template <class R, int Q = 0>
-__device__ inline void recolour(R *g, const R *d, const CellState<R> &c, R rec, R iFn)
+__device__ inline void collide_h(R *h, R om1d, const R H[3], const R vs[3])
 {
-    constexpr R w = weight<R>(Q);
-    const R ft = w + d[Q];
+    constexpr int k = Q == 0 ? 0 : (Q <= 6 ? 1 : 2);
     if constexpr (Q == 0) {
-        g[Q] = c.C * ft;
+        h[Q] = fma(om1d, h[Q], H[0]);
     } else {
-        constexpr R inv_len = speed2(Q) == 1 ? R(1) : R(0.70710678118654752440);
-        const R cG = R(cx(Q)) * c.F[0] + R(cy(Q)) * c.F[1] + R(cz(Q)) * c.F[2];
-        g[Q] = c.C * ft + rec * w * cG * inv_len * iFn;
+        const R cv = cdot<R, Q>(vs);
+        h[Q] = fma(om1d, h[Q], fma(R(3) * H[k], cv, H[k]));
     }
-    if constexpr (Q + 1 < NQ) recolour<R, Q + 1>(g, d, c, rec, iFn);
+    if constexpr (Q + 1 < NQ) collide_h<R, Q + 1>(h, om1d, H, vs);
 }
 
-template <class S, int Q = 0>
-__device__ inline void store_all(S *__restrict__ P, size_t n, uint32_t idx, const typename Codec<S>::R *v)
+// Two-fluid recolouring: g' = C f' + beta C (1 - C) rho w cos(v, F).
+template <class R, int Q = 0>
+__device__ inline void recolour(R *g, const R *d, R C, const R Cw[3], const R rw[3], const R F[3])
 {
-    Codec<S>::store(P + size_t(Q) * n + idx, v[Q]);
-    if constexpr (Q + 1 < NQ) store_all<S, Q + 1>(P, n, idx, v);
+    constexpr int k = Q == 0 ? 0 : (Q <= 6 ? 1 : 2);
+    if constexpr (Q == 0) {
+        g[Q] = fma(C, d[Q], Cw[0]);
+    } else {
+        const R cG = cdot<R, Q>(F);
+        g[Q] = fma(rw[k], cG, fma(C, d[Q], Cw[k]));
+    }
+    if constexpr (Q + 1 < NQ) recolour<R, Q + 1>(g, d, C, Cw, rw, F);
 }
 
 // Porous velocity and force (Eqs. forcement, expandV, expandVsub with eps on
@@ -326,25 +433,27 @@ template <class R>
 __device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R nu, const R V[3], R u[3], R Fx[3])
 {
     const R G[3] = {R(L->G[0]), R(L->G[1]), R(L->G[2])};
-    R W[3], lam[3], mu[3], sk[3];
+    R W[3], lam[3], ilam[3], mu[3], sk[3];
     R Feps = R(0);
-    if (L->forch) Feps = R(1.75) / sqrt(R(150) * eps * eps * eps);
+    const bool forch = L->forch != 0;
+    if (forch) Feps = R(1.75) / sqrt(R(150) * eps * eps * eps);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         W[a] = V[a] + R(0.5) * eps * G[a];
         lam[a] = R(1) + R(0.5) * eps * nu * kinv[a];
-        sk[a] = sqrt(kinv[a]);
+        ilam[a] = rcp(lam[a]);
+        sk[a] = forch ? sqrt(kinv[a]) : R(0);
         mu[a] = R(0.5) * eps * Feps * sk[a];
     }
-    R s;
-    if (L->forch) {
-        s = solve_speed<R>(W, lam, mu);
-    } else {
-        s = R(0);
-    }
+    if (forch) {
+        const R s = solve_speed<R>(W, lam, mu, ilam);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = W[a] / (lam[a] + mu[a] * s);
-    const R sp = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        for (int a = 0; a < 3; ++a) u[a] = W[a] * rcp(lam[a] + mu[a] * s);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = W[a] * ilam[a];
+    }
+    const R sp = forch ? sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) : R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         Fx[a] = eps * G[a] - eps * nu * kinv[a] * u[a] - eps * Feps * sp * sk[a] * u[a];
@@ -352,7 +461,7 @@ __device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R n
 
 // ---------------------------------------------------------------------------
 // FP64 block reduction of the diagnostic partial sums: wave64 butterfly,
-// then the four waves in a fixed order.  Deterministic.
+// then the waves of the block in a fixed order.  Deterministic.
 __device__ inline void block_reduce_store(double v[NPART], double *out)
 {
     __shared__ double red[BLOCK / 64][NPART];
@@ -406,7 +515,7 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 // The step kernel: pull-stream both lattices, moments, viscosity, porous
 // force, (colour gradient), collide, write the other copy.
 template <int PHYS, class S>
-__global__ __launch_bounds__(BLOCK) void k_step(const BatchArgs a)
+__global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
     const int gb = xcd_remap(blockIdx.x, a.total_blocks);
@@ -419,7 +528,6 @@ __global__ __launch_bounds__(BLOCK) void k_step(const BatchArgs a)
     const R nuc = R(a.nuc[l]);
 
     const uint32_t ncell = L->ncell;
-    const size_t n = ncell;
     const uint32_t idx = uint32_t(lb) * BLOCK + threadIdx.x;
     const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
 
@@ -438,105 +546,104 @@ __global__ __launch_bounds__(BLOCK) void k_step(const BatchArgs a)
     if (type == CELL_FLUID) {
         const Nbr b = neighbours(L, x, y, z);
         R d[NQ];
-        pull_all<S>(static_cast<const S *>(L->f[src]), n, idx, b, d);
+        pull_all<S>(L->f[src], ncell, idx, b, d);
         R hq[NQ];
-        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(static_cast<const S *>(L->h[src]), n, idx, b, hq);
+        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], ncell, idx, b, hq);
 
-        CellState<R> c;
-        R jx = 0, jy = 0, jz = 0;
-        c.drho = 0;
-        moments_acc<R>(d, c.drho, jx, jy, jz);
-        c.rho = R(1) + c.drho;
-        const R irho = R(1) / c.rho;
+        R drho = 0, jx = 0, jy = 0, jz = 0;
+        moments_acc<R>(d, drho, jx, jy, jz);
+        const R rho = R(1) + drho;
+        const R irho = rcp(rho);
         const R V[3] = {jx * irho, jy * irho, jz * irho};
 
-        c.eps = L->uniform_eps ? R(L->eps_u) : static_cast<const R *>(L->eps)[idx];
+        const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
         R kinv[3];
         if (L->uniform_kinv) {
             kinv[0] = R(L->kinv_u[0]);
             kinv[1] = R(L->kinv_u[1]);
             kinv[2] = R(L->kinv_u[2]);
         } else {
-            const R *K = static_cast<const R *>(L->kinv);
-            kinv[0] = K[idx];
-            kinv[1] = K[n + idx];
-            kinv[2] = K[2 * n + idx];
+            kinv[0] = ldg<R>(L->kinv, idx);
+            kinv[1] = ldg<R>(L->kinv, ncell + idx);
+            kinv[2] = ldg<R>(L->kinv, 2 * ncell + idx);
         }
-        const R ie = R(1) / c.eps;
+        const R ie = rcp(eps);
 
-        R sh = 0, rho1 = 0;
-        c.C = 0;
+        R sh = 0, rho1 = 0, C = 0;
         if constexpr (PHYS == PH_MISCIBLE) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) sh += hq[q];
-            c.C = sh * ie;
+            C = sh * ie;
         } else if constexpr (PHYS == PH_IMMISCIBLE) {
-            rho1 = static_cast<const R *>(L->rho1)[idx];
-            c.C = rho1 * irho;
+            rho1 = ldg<R>(L->rho1, idx);
+            C = rho1 * irho;
         }
 
         R nu;
         if constexpr (PHYS == PH_IMMISCIBLE) {
-            nu = c.C * R(L->nu1) + (R(1) - c.C) * R(L->nu2);
+            nu = C * R(L->nu1) + (R(1) - C) * R(L->nu2);
         } else if constexpr (PHYS == PH_MISCIBLE) {
-            nu = nuc * exp(R(L->k1) * c.C + R(L->k0));
+            nu = nuc * exp(R(L->k1) * C + R(L->k0));
         } else {
             nu = nuc * exp(R(L->k0));
         }
-        c.tau = R(0.5) + R(3) * nu;
-        c.omega = R(1) / c.tau;
+        const R tau = R(0.5) + R(3) * nu;
+        const R omega = rcp(tau);
 
-        porous_force<R>(L, c.eps, kinv, nu, V, c.u, c.Fx);
+        R u[3], Fx[3];
+        porous_force<R>(L, eps, kinv, nu, V, u, Fx);
 
-        c.F[0] = c.F[1] = c.F[2] = R(0);
-        c.Fn = R(0);
+        R F[3] = {0, 0, 0};
+        R Fn = 0, iFn = 0, st = 0;
         if constexpr (PHYS == PH_IMMISCIBLE) {
-            colour_acc<R>(static_cast<const R *>(L->rho1), b, c.F[0], c.F[1], c.F[2]);
-            c.Fn = sqrt(c.F[0] * c.F[0] + c.F[1] * c.F[1] + c.F[2] * c.F[2]);
+            colour_acc<R>(L->rho1, b, F[0], F[1], F[2]);
+            Fn = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+            iFn = Fn > R(0) ? rcp(Fn) : R(0);
+            st = Fn > R(0) ? R(L->A) * eps * tau : R(0);
         }
-        const R iFn = c.Fn > R(0) ? R(1) / c.Fn : R(0);
-        const R st = c.Fn > R(0) ? R(L->A) * c.eps * c.tau : R(0);
-        const R uu = c.u[0] * c.u[0] + c.u[1] * c.u[1] + c.u[2] * c.u[2];
-        const R uF = c.u[0] * c.Fx[0] + c.u[1] * c.Fx[1] + c.u[2] * c.Fx[2];
-        const R pre = R(1) - R(0.5) * c.omega;
-        collide_f<R>(d, c, st, iFn, ie, uu, uF, pre);
+        const Coll<R> cl = make_coll<R>(drho, rho, omega, ie, u, Fx, st, F, Fn, iFn);
+        collide_f<R, PHYS == PH_IMMISCIBLE>(d, cl);
 
         const int dst = src ^ 1;
         if constexpr (PHYS == PH_MISCIBLE) {
-            R vs[3] = {c.u[0], c.u[1], c.u[2]};
+            R vs[3] = {u[0], u[1], u[2]};
             if (L->eps_grad && !L->uniform_eps) {
                 R gx = 0, gy = 0, gz = 0;
-                eps_grad_acc<R>(static_cast<const R *>(L->eps), b, c.eps, gx, gy, gz);
+                eps_grad_acc<R>(L->eps, b, eps, gx, gy, gz);
                 const R k = R(3) * R(L->D) * ie;
                 vs[0] += k * gx;
                 vs[1] += k * gy;
                 vs[2] += k * gz;
             }
-            collide_h<R>(hq, sh, vs, R(1) / R(L->tau_d));
-            store_all<S>(static_cast<S *>(L->h[dst]), n, idx, hq);
+            const R omd = R(1) / R(L->tau_d);
+            const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
+            collide_h<R>(hq, R(1) - omd, H, vs);
+            store_all<S>(L->h[dst], ncell, idx, hq);
         } else if constexpr (PHYS == PH_IMMISCIBLE) {
             R g[NQ];
-            const R rec = c.Fn > R(0) ? R(L->beta) * c.C * (R(1) - c.C) * c.rho : R(0);
-            recolour<R>(g, d, c, rec, iFn);
-            store_all<S>(static_cast<S *>(L->h[dst]), n, idx, g);
+            const R rec = Fn > R(0) ? R(L->beta) * C * (R(1) - C) * rho * iFn : R(0);
+            const R Cw[3] = {C * weight<R>(0), C * weight<R>(1), C * weight<R>(7)};
+            const R rw[3] = {R(0), rec * weight<R>(1), rec * weight<R>(7) * R(0.70710678118654752440)};
+            recolour<R>(g, d, C, Cw, rw, F);
+            store_all<S>(L->h[dst], ncell, idx, g);
         }
-        store_all<S>(static_cast<S *>(L->f[dst]), n, idx, d);
+        store_all<S>(L->f[dst], ncell, idx, d);
 
         if (mom) {
-            R *M = static_cast<R *>(L->mom);
-            const R up[3] = {M[n + idx], M[2 * n + idx], M[3 * n + idx]};
-            M[idx] = c.rho;
-            M[n + idx] = c.u[0];
-            M[2 * n + idx] = c.u[1];
-            M[3 * n + idx] = c.u[2];
-            M[4 * n + idx] = c.C;
+            void *M = L->mom;
+            const R up[3] = {ldg<R>(M, ncell + idx), ldg<R>(M, 2 * ncell + idx), ldg<R>(M, 3 * ncell + idx)};
+            stg<R>(M, idx, rho);
+            stg<R>(M, ncell + idx, u[0]);
+            stg<R>(M, 2 * ncell + idx, u[1]);
+            stg<R>(M, 3 * ncell + idx, u[2]);
+            stg<R>(M, 4 * ncell + idx, C);
             has = true;
-            m_rho = c.rho;
-            m_C = c.C;
+            m_rho = rho;
+            m_C = C;
             m_s4 = PHYS == PH_MISCIBLE ? sh : (PHYS == PH_IMMISCIBLE ? rho1 : R(0));
-            for (int a = 0; a < 3; ++a) {
-                m_u[a] = c.u[a];
-                m_up[a] = up[a];
+            for (int k = 0; k < 3; ++k) {
+                m_u[k] = u[k];
+                m_up[k] = up[k];
             }
         }
     }
@@ -578,12 +685,12 @@ __global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
     } else {
         const Nbr b = neighbours(L, x, y, z);
         R g[NQ];
-        pull_all<S>(static_cast<const S *>(L->h[src]), ncell, idx, b, g);
+        pull_all<S>(L->h[src], ncell, idx, b, g);
         v = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v += g[q];
     }
-    static_cast<R *>(L->rho1)[idx] = v;
+    stg<R>(L->rho1, idx, v);
 }
 
 // Second stage of the diagnostics: one block per lattice sums the per-block
@@ -640,7 +747,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_colour(const InitArgs<R> ia)
     if (type == CELL_SOLID) v = R(L->face_cw[face]);
     else if (type == CELL_RES) v = R(L->face_conc[face]) * R(L->face_rho[face]);
     else v = (ia.c0 ? ia.c0[idx] : R(0)) * (ia.rho0 ? ia.rho0[idx] : R(1));
-    static_cast<R *>(L->rho1)[idx] = v;
+    stg<R>(L->rho1, idx, v);
 }
 
 // initial populations (flowchart: f = f^eq, h = h^eq from the fields), the
@@ -661,10 +768,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
     int face;
     const int type = cell_type(L, x, y, z, face);
 
-    const R eps = L->uniform_eps ? R(L->eps_u) : static_cast<const R *>(L->eps)[idx];
+    const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
     R kinv[3];
-    for (int a = 0; a < 3; ++a)
-        kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : static_cast<const R *>(L->kinv)[a * n + idx];
+    for (int a = 0; a < 3; ++a) kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : ldg<R>(L->kinv, a * ncell + idx);
     const R rho0 = ia.rho0 ? ia.rho0[idx] : R(1);
     R u0[3];
     for (int a = 0; a < 3; ++a) u0[a] = ia.vel0 ? ia.vel0[a * n + idx] : R(0);
@@ -691,46 +797,42 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
         mC = PHYS == PH_SINGLE ? R(0) : cb;
     } else {
         const Nbr b = neighbours(L, x, y, z);
-        CellState<R> c;
-        c.drho = rho0 - R(1);
-        c.rho = rho0;
-        c.eps = eps;
-        c.C = PHYS == PH_SINGLE ? R(0) : c0;
+        const R C = PHYS == PH_SINGLE ? R(0) : c0;
         R nu;
-        if constexpr (PHYS == PH_IMMISCIBLE) nu = c.C * R(L->nu1) + (R(1) - c.C) * R(L->nu2);
-        else nu = R(ia.nuc0) * exp(R(L->k1) * (PHYS == PH_MISCIBLE ? c.C : R(0)) + R(L->k0));
-        c.tau = R(0.5) + R(3) * nu;
-        c.omega = R(1);           // d := f^eq below
-        for (int a = 0; a < 3; ++a) {
-            c.u[a] = u0[a];
-            c.Fx[a] = R(0);
-            c.F[a] = R(0);
-        }
-        c.Fn = R(0);
+        if constexpr (PHYS == PH_IMMISCIBLE) nu = C * R(L->nu1) + (R(1) - C) * R(L->nu2);
+        else nu = R(ia.nuc0) * exp(R(L->k1) * (PHYS == PH_MISCIBLE ? C : R(0)) + R(L->k0));
+        const R tau = R(0.5) + R(3) * nu;
+        R F[3] = {0, 0, 0};
+        R Fn = 0;
         if constexpr (PHYS == PH_IMMISCIBLE) {
-            colour_acc<R>(static_cast<const R *>(L->rho1), b, c.F[0], c.F[1], c.F[2]);
-            c.Fn = sqrt(c.F[0] * c.F[0] + c.F[1] * c.F[1] + c.F[2] * c.F[2]);
+            colour_acc<R>(L->rho1, b, F[0], F[1], F[2]);
+            Fn = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
         }
-        const R iFn = c.Fn > R(0) ? R(1) / c.Fn : R(0);
-        const R st = c.Fn > R(0) ? R(L->A) * eps * c.tau : R(0);
-        const R uu = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+        const R iFn = Fn > R(0) ? R(1) / Fn : R(0);
+        const R st = Fn > R(0) ? R(L->A) * eps * tau : R(0);
+        const R zero3[3] = {0, 0, 0};
         for (int q = 0; q < NQ; ++q) d[q] = R(0);
-        // with omega = 1 and no force the collision returns f^eq exactly
-        collide_f<R>(d, c, st, iFn, R(1) / eps, uu, R(0), R(0));
+        // with omega = 1 and no force the collision returns f^eq
+        const Coll<R> cl = make_coll<R>(rho0 - R(1), rho0, R(1), R(1) / eps, u0, zero3, st, F, Fn, iFn);
+        collide_f<R, PHYS == PH_IMMISCIBLE>(d, cl);
         if constexpr (PHYS == PH_MISCIBLE) {
             R vs[3] = {u0[0], u0[1], u0[2]};
             if (L->eps_grad && !L->uniform_eps) {
                 R gx = 0, gy = 0, gz = 0;
-                eps_grad_acc<R>(static_cast<const R *>(L->eps), b, eps, gx, gy, gz);
+                eps_grad_acc<R>(L->eps, b, eps, gx, gy, gz);
                 const R k = R(3) * R(L->D) / eps;
                 vs[0] += k * gx;
                 vs[1] += k * gy;
                 vs[2] += k * gz;
             }
             for (int q = 0; q < NQ; ++q) hq[q] = R(0);
-            collide_h<R>(hq, eps * c0, vs, R(1));
+            const R ec = eps * c0;
+            const R H[3] = {weight<R>(0) * ec, weight<R>(1) * ec, weight<R>(7) * ec};
+            collide_h<R>(hq, R(0), H, vs);
         } else if constexpr (PHYS == PH_IMMISCIBLE) {
-            recolour<R>(hq, d, c, R(0), R(0));
+            const R Cw[3] = {C * weight<R>(0), C * weight<R>(1), C * weight<R>(7)};
+            const R rw[3] = {0, 0, 0};
+            recolour<R>(hq, d, C, Cw, rw, F);
         } else {
             for (int q = 0; q < NQ; ++q) hq[q] = R(0);
         }
@@ -738,18 +840,18 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
         mu[0] = u0[0];
         mu[1] = u0[1];
         mu[2] = u0[2];
-        mC = c.C;
+        mC = C;
     }
     for (int cpy = 0; cpy < 2; ++cpy) {
-        store_all<S>(static_cast<S *>(L->f[cpy]), n, idx, d);
-        if constexpr (PHYS != PH_SINGLE) store_all<S>(static_cast<S *>(L->h[cpy]), n, idx, hq);
+        store_all<S>(L->f[cpy], ncell, idx, d);
+        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], ncell, idx, hq);
     }
-    R *M = static_cast<R *>(L->mom);
-    M[idx] = mrho;
-    M[n + idx] = mu[0];
-    M[2 * n + idx] = mu[1];
-    M[3 * n + idx] = mu[2];
-    M[4 * n + idx] = mC;
+    void *M = L->mom;
+    stg<R>(M, idx, mrho);
+    stg<R>(M, ncell + idx, mu[0]);
+    stg<R>(M, 2 * ncell + idx, mu[1]);
+    stg<R>(M, 3 * ncell + idx, mu[2]);
+    stg<R>(M, 4 * ncell + idx, mC);
 }
 
 // diagnostics of the moments buffer (used after set-up: residual 0)
@@ -757,7 +859,6 @@ template <class R>
 __global__ __launch_bounds__(BLOCK) void k_diag_moments(const LatDev *L)
 {
     const uint32_t ncell = L->ncell;
-    const size_t n = ncell;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (idx < ncell) {
@@ -767,14 +868,14 @@ __global__ __launch_bounds__(BLOCK) void k_diag_moments(const LatDev *L)
         const int y = r / nx, x = r - uint32_t(y) * nx;
         int face;
         if (cell_type(L, x, y, z, face) == CELL_FLUID) {
-            const R *M = static_cast<const R *>(L->mom);
-            const R u[3] = {M[n + idx], M[2 * n + idx], M[3 * n + idx]};
-            const R rho = M[idx], C = M[4 * n + idx];
+            const void *M = L->mom;
+            const R u[3] = {ldg<R>(M, ncell + idx), ldg<R>(M, 2 * ncell + idx), ldg<R>(M, 3 * ncell + idx)};
+            const R rho = ldg<R>(M, idx), C = ldg<R>(M, 4 * ncell + idx);
             R s4 = 0;
             if (L->physics == PH_MISCIBLE)
-                s4 = (L->uniform_eps ? R(L->eps_u) : static_cast<const R *>(L->eps)[idx]) * C;
+                s4 = (L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx)) * C;
             else if (L->physics == PH_IMMISCIBLE)
-                s4 = static_cast<const R *>(L->rho1)[idx];
+                s4 = ldg<R>(L->rho1, idx);
             diag_contrib<R>(part, rho, u, C, s4, u);
         }
     }
@@ -788,8 +889,8 @@ __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, in
     const uint32_t ncell = L->ncell;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= ncell) return;
-    const S *P = static_cast<const S *>(which == 0 ? L->f[src] : L->h[src]);
-    for (int q = 0; q < NQ; ++q) dst[size_t(q) * ncell + idx] = Codec<S>::load(P + size_t(q) * ncell + idx);
+    const void *P = which == 0 ? L->f[src] : L->h[src];
+    for (int q = 0; q < NQ; ++q) dst[size_t(q) * ncell + idx] = Codec<S>::load(at(plane<S>(P, ncell, q), idx));
 }
 
 }  // namespace plbm
