@@ -284,6 +284,11 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     D.nz = d->nz;
     D.ncell = int(n);
     D.nblocks = h->nblocks;
+    {
+        const size_t plane_cells = (size_t)d->nx * d->ny;
+        const size_t bpp = plane_cells / BLOCK;
+        D.bpp = (PLBM_SLAB && plane_cells % BLOCK == 0 && bpp % 8 == 0) ? int(bpp) : 0;
+    }
     D.physics = d->physics;
     D.forch = d->forchheimer ? 1 : 0;
     D.eps_grad = d->eps_gradient ? 1 : 0;
