@@ -64,6 +64,33 @@ def time_gpu(problem, storage, steps, warmup):
     return ms, dg
 
 
+def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50):
+    """The serving workload: 64 requests, Poisson arrivals at 4/s, cubic edge
+    log-uniform in [48, 192], 70% miscible / 30% two-fluid, 500-5000 steps,
+    seeded spruce-like media (anisotropy U[10, 200]), admitted under an HBM
+    budget with lattices resident on the device (continuous batching)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_0912_4230_amd import inputs as I
+    from paper_0912_4230_amd.serve import GpuExecutor, serve
+    reqs = I.request_stream()
+    log("bench: generating the 64 request media")
+    with ThreadPoolExecutor(8) as pool:
+        probs = dict(zip([r.rid for r in reqs], pool.map(I.request_problem, reqs)))
+    out = {"requests": len(reqs), "arrival_rate_per_s": 4.0, "budget_GB": budget_gb, "tick_steps": tick_steps,
+           "offered_GLUP": round(sum(r.edge ** 3 * r.steps for r in reqs) / 1e9, 2),
+           "percentile_rule": "nearest rank over the 64 latencies (p99 = the largest)"}
+    for st in storages:
+        log(f"bench: serving {st}")
+        ex = GpuExecutor(storage=st, problems=probs)
+        res = serve(reqs, ex, int(budget_gb * 1e9), tick_steps=tick_steps)
+        out[st] = {"p50_s": round(res["p50_s"], 3), "p99_s": round(res["p99_s"], 3),
+                   "mean_s": round(res["mean_s"], 3), "aggregate_MLUPS": round(res["aggregate_mlups"], 1),
+                   "completed": res["completed"], "failed": res["failed"], "max_active": res["max_active"],
+                   "span_s": round(res["span_s"], 2)}
+        log(f"bench: serving {st}: {out[st]}")
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -92,6 +119,7 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the lattice update is not sharded across GPUs in this "
@@ -152,6 +180,8 @@ def main():
                        "speedup_vs_f32": round(ms_step / s2, 3)}
             log(f"bench: {st}: {s2:.4f} ms/step, speedup {ms_step / s2:.3f}")
         out["reduced_storage"] = red
+    if not args.no_serve:
+        out["serving"] = serving_leg()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()
