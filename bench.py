@@ -45,6 +45,21 @@ def ensure_built():
         __graft_entry__.build()
 
 
+def counter_traffic(key):
+    """HBM bytes per launch of a kernel from the committed counter record
+    (profiles/traffic.json), in GB -- or None when the kernel sources have
+    changed since the counters were taken."""
+    import json as _json
+    from paper_0912_4230_amd.prof_summary import source_sha
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = _json.load(open(path))
+    if rec.get("source_sha256") != source_sha() or key not in rec:
+        return None
+    return round(rec[key]["bytes"] / 1e9, 4)
+
+
 def time_gpu(problem, storage, steps, warmup):
     import torch
     from paper_0912_4230_amd.sim import Simulation
@@ -165,7 +180,10 @@ def main():
                                "inlet/outlet reservoirs", "grid": [n, n, n], "cells": ncell,
                    "diag_every": 100},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counter_traffic(f"k_step miscible {n} {args.storage}"),
+                     "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_GB_per_launch": round(bpl * ncell / 1e9, 4),
                      "bytes_per_lup": bpl, "kernel": "k_step<miscible>"},
         "diag_final": {"sum_rho": dg[0], "sum_epsC": dg[4], "max_v": dg[6], "nonfinite": dg[7]},
     }
@@ -177,7 +195,8 @@ def main():
             b2 = bytes_per_lup(2, 4)
             red[st] = {"MLUPS": round(ncell * args.steps / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(s2, 5),
                        "bytes_per_lup": b2, "achieved_GBs": round(b2 * ncell / (s2 / 1e3) / 1e9, 1),
-                       "speedup_vs_f32": round(ms_step / s2, 3)}
+                       "speedup_vs_f32": round(ms_step / s2, 3),
+                       "traffic_GB_per_launch": counter_traffic(f"k_step miscible {n} {st}")}
             log(f"bench: {st}: {s2:.4f} ms/step, speedup {ms_step / s2:.3f}")
         out["reduced_storage"] = red
     if not args.no_serve:
