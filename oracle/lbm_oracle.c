@@ -542,6 +542,7 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
     if (p->physics == PHYS_IMMISCIBLE) colour_field(s, 0);
 
     int nx = p->nx, ny = p->ny, nz = p->nz;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {

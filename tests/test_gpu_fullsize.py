@@ -1,0 +1,140 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: after n GPU steps the state is exported and loaded into the FP64
+oracle, which computes one more step for sampled cells (interior cells plus
+cells next to reservoirs and walls); the GPU's next step must match on those
+cells.  The oracle works in FP64 from the same (FP32-rounded) state, so the
+difference measures the FP32 arithmetic of one step only.
+
+Also the precision form on the 64^3 crop of the seeded medium, BF16/FP16
+(and FP32) against the FP64 oracle after 2000 steps.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import ensure_built, errors, need_gpu, permutation_to_oracle, rel_l2, report
+from paper_0912_4230_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    need_gpu()
+    ensure_built()
+
+
+def _samples(shape, rng, extra):
+    nx, ny, nz = shape
+    k = 3000
+    x = rng.integers(0, nx, k)
+    y = rng.integers(0, ny, k)
+    z = rng.integers(0, nz, k)
+    cells = set((x + nx * (y + ny * z)).tolist())
+    for (a, b, c) in extra:
+        cells.add(a + nx * (b + ny * c))
+    return np.array(sorted(cells), dtype=np.int64)
+
+
+def _one_step_parity(problem, n0, storage, extra, pop_tol, rho_tol, c_tol):
+    from oracle import oracle as O
+    from paper_0912_4230_amd.sim import Simulation
+    nx, ny, nz = problem.shape
+    sim = Simulation(problem, storage=storage, diag_every=100)
+    sim.step(n0)
+    perm = permutation_to_oracle()
+    inv = np.argsort(perm)          # oracle q -> gpu q
+    f0 = sim.populations(0).double().cpu().numpy().reshape(19, -1)
+    h0 = sim.populations(1).double().cpu().numpy().reshape(19, -1) if problem.physics != I.SINGLE else None
+    sim.step(1)
+    rho, vel, conc, dg = sim.moments()
+    f1 = sim.populations(0).double().cpu().numpy().reshape(19, -1)
+    h1 = sim.populations(1).double().cpu().numpy().reshape(19, -1) if problem.physics != I.SINGLE else None
+    rho = rho.double().cpu().numpy().reshape(-1)
+    vel = vel.double().cpu().numpy().reshape(3, -1)
+    conc = conc.double().cpu().numpy().reshape(-1)
+    sim.close()
+
+    o = O.Oracle(problem)
+    o.set_state(0, f0[inv], n0)
+    if h0 is not None:
+        o.set_state(1, h0[inv], n0)
+    del f0, h0
+    cells = _samples(problem.shape, np.random.default_rng(7), extra)
+    types = o.cell_types().reshape(-1)[cells]
+    fo, ho, mo = o.step_cells(cells)
+    o.close()
+    fluid = types == 0
+    fg = f1[:, cells].T[:, inv]             # (k, 19) in oracle order
+    df = np.abs(fg - fo)[fluid].max()
+    dh = np.abs(h1[:, cells].T[:, inv] - ho)[fluid].max() if h1 is not None else 0.0
+    drho = np.abs(rho[cells] - mo[:, 0])[fluid].max()
+    dc = np.abs(conc[cells] - mo[:, 4])[fluid].max()
+    du = np.abs(vel[:, cells].T - mo[:, 1:4])[fluid].max()
+    umax = np.abs(mo[:, 1:4][fluid]).max()
+    print(f"[fullsize] {problem.shape} {storage} n0={n0} cells={fluid.sum()}: max|df|={df:.2e} "
+          f"max|dh|={dh:.2e} max|drho|={drho:.2e} max|dC|={dc:.2e} max|dV'|={du:.2e} (max|V'|={umax:.2e})",
+          flush=True)
+    assert fluid.sum() > 1000
+    assert df < pop_tol and dh < pop_tol
+    assert drho < rho_tol and dc < c_tol
+    assert du < 1e-5 * max(umax, 1e-3)
+    # non-fluid sampled cells hold their fixed state (reservoirs) or zeros (walls)
+    if (~fluid).any():
+        assert np.abs(fg - fo)[~fluid].max() < 1e-6
+
+
+def test_miscible_256_one_step():
+    n = 256
+    p = I.miscible(shape=(n, n, n), seed=0)
+    extra = [(1, 5, 9), (2, 100, 200), (n - 2, 17, 33), (n - 3, n - 1, 0), (0, 3, 3), (n - 1, 4, 4)]
+    _one_step_parity(p, 40, "f32", extra, pop_tol=2e-7, rho_tol=1e-6, c_tol=1e-6)
+
+
+def test_two_fluid_drop_128_one_step():
+    n = 128
+    p = I.drop(shape=(n, n, n), radius=20.0, speed=0.05)
+    # through the drop's interface and next to both walls
+    extra = [(64, 64, 44), (64, 64, 45), (64, 84, 64), (84, 64, 64), (10, 20, 1), (30, 40, n - 2),
+             (64, 64, 0), (64, 64, n - 1)]
+    _one_step_parity(p, 60, "f32", extra, pop_tol=2e-7, rho_tol=1e-6, c_tol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def crop_oracle():
+    from oracle import oracle as O
+    p = I.miscible(shape=(64, 64, 64), seed=0)
+    o = O.Oracle(p)
+    o.step(2000)
+    r = o.moments()
+    mask = o.cell_types() == 0
+    o.close()
+    return p, r, mask
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_precision_form_crop_vs_oracle(storage, crop_oracle):
+    """The 512^3 precision-form physics on the 64^3 crop [0,64)^3 of the same
+    seeded medium (own reservoirs at x = 0 and 63), 2000 steps, 16-bit storage
+    against the FP64 oracle; errors are stated per field (bounds from
+    measurement), with the FP32 path alongside."""
+    from paper_0912_4230_amd.sim import Simulation
+    p, r, mask = crop_oracle
+    out = {}
+    for st in ("f32", storage):
+        sim = Simulation(p, storage=st)
+        sim.step(2000)
+        rho, vel, conc, dg = sim.moments()
+        g = (rho.double().cpu().numpy(), vel.double().cpu().numpy(), conc.double().cpu().numpy())
+        out[st] = errors(g, r, mask)
+        report(f"precision crop 64^3 x2000 {st}", out[st])
+        sim.close()
+    e = out[storage]
+    # measured (MI355X): BF16 rho 3.9e-3, drho 0.40, V' 0.83, C 0.18;
+    # FP16 rho 3.3e-4, drho 0.035, V' 0.066, C 4.2e-3; FP32 rho 2.0e-7,
+    # drho 2.0e-5, V' 3.4e-5, C 2.0e-5
+    bounds = {"bf16": {"rho": 5e-3, "drho": 0.5, "vel": 1.0, "conc": 0.25},
+              "f16": {"rho": 5e-4, "drho": 0.05, "vel": 0.1, "conc": 1e-2}}[storage]
+    for k, b in bounds.items():
+        assert e[k] < b, (k, e[k])
+    f = out["f32"]
+    assert f["rho"] < 1e-6 and f["drho"] < 5e-5 and f["vel"] < 1e-4 and f["conc"] < 5e-5
