@@ -106,6 +106,83 @@ def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50):
     return out
 
 
+def medium_parallel(n, seed=0, slabs=16):
+    """The n^3 miscible problem with its medium generated in z-slabs in
+    parallel (the counter-based generator makes every slab equal to the
+    corresponding crop of the full medium)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_0912_4230_amd import inputs as I
+    p = I.miscible(shape=(n, n, 2), seed=seed)
+    p.shape = (n, n, n)
+    dz = (n + slabs - 1) // slabs
+    parts = [(z0, min(dz, n - z0)) for z0 in range(0, n, dz)]
+    eps = np.empty((n, n, n), dtype=np.float32)
+    kinv = np.empty((3, n, n, n), dtype=np.float32)
+
+    def gen(part):
+        z0, nzp = part
+        e, k = I.spruce_medium((n, n, nzp), seed=seed, ratio=100.0, origin=(0, 0, z0))
+        eps[z0:z0 + nzp] = e
+        kinv[:, z0:z0 + nzp] = k
+
+    with ThreadPoolExecutor(8) as pool:
+        list(pool.map(gen, parts))
+    p.eps, p.kinv = eps, kinv
+    p.rho0 = np.ones((n, n, n), dtype=np.float32)
+    p.vel0 = np.zeros((3, n, n, n), dtype=np.float32)
+    p.c0 = np.zeros((n, n, n), dtype=np.float32)
+    return p
+
+
+def precision_leg(n=512, steps=2000, timed=200):
+    """Precision form: the miscible workload at n^3 with FP32, BF16- and
+    FP16-stored populations on the same GPU; step time over `timed` steps,
+    then the run continues to `steps` steps and the 16-bit fields are compared
+    with the FP32 ones over the fluid cells (relative L2)."""
+    import torch
+    from paper_0912_4230_amd.sim import Simulation
+    log(f"bench: generating the {n}^3 medium")
+    p = medium_parallel(n)
+    ncell = n ** 3
+    res = {"grid": [n, n, n], "steps": steps, "timed_steps": timed}
+    ref = None
+    for st in ("f32", "bf16", "f16"):
+        log(f"bench: precision {st}")
+        sim = Simulation(p, storage=st, diag_every=100)
+        sim.step(20)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(sim.stream)
+        sim.step(timed)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / timed
+        sim.step(steps - 20 - timed)
+        rho, vel, conc, dg = sim.moments(check=False)
+        sim.close()
+        del sim
+        fields = (rho[:, :, 1:-1], vel[:, :, :, 1:-1], conc[:, :, 1:-1])   # fluid cells: x in [1, n-2]
+        bpl = bytes_per_lup(4 if st == "f32" else 2, 4)
+        entry = {"ms_per_step": round(ms, 4), "MLUPS": round(ncell / ms / 1e3, 1),
+                 "achieved_GBs": round(bpl * ncell / ms / 1e6, 1), "bytes_per_lup": bpl,
+                 "nonfinite": int(dg[7])}
+        if ref is None:
+            ref = fields
+        else:
+            def rel(x, y):
+                return float(torch.linalg.vector_norm((x - y).double()) / torch.linalg.vector_norm(y.double()))
+            entry["rel_l2_vs_f32"] = {"rho": rel(fields[0], ref[0]), "drho": rel(fields[0] - 1, ref[0] - 1),
+                                      "vel": rel(fields[1], ref[1]), "conc": rel(fields[2], ref[2])}
+            entry["speedup_vs_f32"] = round(res["f32"]["ms_per_step"] / ms, 3)
+        res[st] = entry
+        log(f"bench: precision {st}: {entry}")
+        del rho, vel, conc
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -135,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--precision", action="store_true",
+                    help="also run the 512^3 precision form (FP32 / BF16 / FP16 storage, 2000 steps)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the lattice update is not sharded across GPUs in this "
@@ -201,6 +280,8 @@ def main():
         out["reduced_storage"] = red
     if not args.no_serve:
         out["serving"] = serving_leg()
+    if args.precision:
+        out["precision_form"] = precision_leg()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

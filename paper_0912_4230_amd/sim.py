@@ -73,7 +73,10 @@ class Simulation:
     # ------------------------------------------------------------------
     def _dev(self, a):
         import torch
-        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device, self.dtype)
+        a = np.ascontiguousarray(a)
+        if a.dtype not in (np.float32, np.float64):
+            a = a.astype(np.float64)
+        return torch.from_numpy(a).to(self.device, self.dtype)
 
     def _set_medium(self, p: I.Problem, uniform_medium: bool):
         import torch
