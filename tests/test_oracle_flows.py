@@ -156,6 +156,28 @@ def test_viscosity_law_plateau(orc):
     assert np.abs(v[2] / (-1e-5 / (nu * 100.0)) - 1).max() < 1e-12
 
 
+def test_darcy_law_between_reservoirs(orc):
+    """Low-Reynolds flow through a uniform medium driven by the inlet/outlet
+    reservoirs: the steady state of Eq. momentum without body force is Darcy's
+    law, rho V = -(K / (eps nu)) grad(eps P) with eps P = rho c_s^2 = rho / 3,
+    with the same mass flux through every cross-section."""
+    nx, eps, K, nu = 66, 0.6, 1.0, 0.1
+    p = I.Problem(shape=(nx, 1, 1), physics=I.SINGLE, nu0=nu).fill_defaults()
+    p.eps[:] = eps
+    p.kinv[:] = 1.0 / K
+    p.faces[0] = I.Face(kind=I.RESERVOIR, rho=1.01)
+    p.faces[1] = I.Face(kind=I.RESERVOIR, rho=1.0)
+    o, r, v, c = _run(orc, p, 3000)
+    rho, u = r[0, 0], v[0, 0, 0]
+    J = rho * u
+    interior = slice(8, nx - 8)
+    assert np.abs(J[interior] / J[interior].mean() - 1).max() < 1e-7
+    grad = 0.5 * (rho[2:] - rho[:-2])                       # centred difference at x = 1..nx-2
+    darcy = -(K / (3.0 * eps * nu)) * grad
+    assert np.abs(J[1:-1][7:nx - 9] / darcy[7:nx - 9] - 1).max() < 1e-5
+    assert J.mean() > 0 and rho[1] > rho[-2]
+
+
 def test_two_fluid_mixture_viscosity_plateau(orc):
     """Uniform colour C: no interface, so the plateau is G K / (C nu_1 + (1 - C) nu_2)."""
     p = I.Problem(shape=(3, 2, 4), physics=I.IMMISCIBLE, G=(3e-5, 0.0, 0.0), tau1=0.7, tau2=1.0,
