@@ -29,8 +29,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update of the miscible step: both lattices
 # read and written once (2 x 19 x 2 populations) + porosity + 3 K^-1 values
-def bytes_per_lup(storage_bytes, real_bytes=4):
-    return 2 * 19 * 2 * storage_bytes + 4 * real_bytes
+def bytes_per_lup(storage_bytes, real_bytes=4, split=False):
+    # split 16-bit storage adds one FP32 mass per cell and lattice, read and written
+    return 2 * 19 * 2 * storage_bytes + 4 * real_bytes + (2 * 2 * 4 if split else 0)
+
+
+def storage_bpl(st):
+    return {"f64": bytes_per_lup(8, 8), "f32": bytes_per_lup(4), "bf16": bytes_per_lup(2), "f16": bytes_per_lup(2),
+            "bf16s": bytes_per_lup(2, split=True), "f16s": bytes_per_lup(2, split=True)}[st]
 
 
 def log(msg):
@@ -147,7 +153,7 @@ def precision_leg(n=512, steps=2000, timed=200):
     ncell = n ** 3
     res = {"grid": [n, n, n], "steps": steps, "timed_steps": timed}
     ref = None
-    for st in ("f32", "bf16", "f16"):
+    for st in ("f32", "bf16", "f16", "bf16s", "f16s"):
         log(f"bench: precision {st}")
         sim = Simulation(p, storage=st, diag_every=100)
         sim.step(20)
@@ -164,7 +170,7 @@ def precision_leg(n=512, steps=2000, timed=200):
         sim.close()
         del sim
         fields = (rho[:, :, 1:-1], vel[:, :, :, 1:-1], conc[:, :, 1:-1])   # fluid cells: x in [1, n-2]
-        bpl = bytes_per_lup(4 if st == "f32" else 2, 4)
+        bpl = storage_bpl(st)
         entry = {"ms_per_step": round(ms, 4), "MLUPS": round(ncell / ms / 1e3, 1),
                  "achieved_GBs": round(bpl * ncell / ms / 1e6, 1), "bytes_per_lup": bpl,
                  "nonfinite": int(dg[7])}
@@ -268,10 +274,10 @@ def main():
     }
     if not args.no_reduced and args.storage == "f32":
         red = {}
-        for st in ("bf16", "f16"):
+        for st in ("bf16", "f16", "bf16s", "f16s"):
             ms2, dg2 = time_gpu(p, st, args.steps, args.warmup)
             s2 = ms2 / args.steps
-            b2 = bytes_per_lup(2, 4)
+            b2 = storage_bpl(st)
             red[st] = {"MLUPS": round(ncell * args.steps / (ms2 / 1e3) / 1e6, 1), "ms_per_step": round(s2, 5),
                        "bytes_per_lup": b2, "achieved_GBs": round(b2 * ncell / (s2 / 1e3) / 1e9, 1),
                        "speedup_vs_f32": round(ms_step / s2, 3),

@@ -67,12 +67,19 @@ typedef enum {
     LBM_F64 = 0,         /* populations and fields in double */
     LBM_F32 = 1,         /* populations and fields in float */
     LBM_BF16_DEV = 2,    /* populations stored in bfloat16, compute in float */
-    LBM_F16_DEV = 3      /* populations stored in IEEE half, compute in float */
+    LBM_F16_DEV = 3,     /* populations stored in IEEE half, compute in float */
+    LBM_BF16_SPLIT = 4,  /* per-cell FP32 mass + bfloat16 remainders, compute in float */
+    LBM_F16_SPLIT = 5    /* per-cell FP32 mass + IEEE half remainders, compute in float */
 } lbm_storage;
 /* The hydrodynamic populations are stored as deviations f_i - w_i from the
  * rest-state weights in every storage mode (in reduced precision this is
  * what makes 16-bit storage usable); the second lattice is stored as is.
- * Rounding to 16 bits is round-to-nearest-even. */
+ * The split modes store, per lattice and cell, m = sum_i of the stored
+ * values in FP32 and the remainders (value_i - w_i m) in 16 bits: the
+ * density (or solute mass) part of every population is then exact to FP32
+ * and only the velocity / non-equilibrium part is rounded to 16 bits
+ * (4 more bytes per cell and lattice, read and written).  Rounding to 16 bits
+ * is round-to-nearest-even. */
 
 typedef enum {
     LBM_FACE_PERIODIC = 0,   /* both faces of an axis must be periodic together */

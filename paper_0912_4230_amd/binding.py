@@ -14,10 +14,11 @@ LIB_PATH = os.path.join(HERE, "libporolbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = range(6)
 LBM_SINGLE, LBM_MISCIBLE, LBM_IMMISCIBLE = range(3)
-LBM_F64, LBM_F32, LBM_BF16_DEV, LBM_F16_DEV = range(4)
+LBM_F64, LBM_F32, LBM_BF16_DEV, LBM_F16_DEV, LBM_BF16_SPLIT, LBM_F16_SPLIT = range(6)
 LBM_FACE_PERIODIC, LBM_FACE_WALL, LBM_FACE_RESERVOIR = range(3)
 
-STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV}
+STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV,
+                 "bf16s": LBM_BF16_SPLIT, "f16s": LBM_F16_SPLIT}
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_medium", "lbm_step", "lbm_step_batch",
             "lbm_moments", "lbm_populations", "lbm_steps_done", "lbm_destroy", "lbm_lattice",
             "lbm_strerror"]

@@ -72,12 +72,14 @@ template <class S> struct Codec;
 
 template <> struct Codec<double> {
     using R = double;
+    static constexpr bool split = false;
     __device__ static R load(const GL double *p) { return ld(p); }
     __device__ static void store(GL double *p, R v) { st(p, v); }
 };
 
 template <> struct Codec<float> {
     using R = float;
+    static constexpr bool split = false;
     __device__ static R load(const GL float *p) { return ld(p); }
     __device__ static void store(GL float *p, R v) { st(p, v); }
 };
@@ -86,9 +88,14 @@ template <> struct Codec<float> {
 // (v_cvt_pk_bf16_f32) rounds to nearest even.
 template <> struct Codec<bf16_t> {
     using R = float;
+    static constexpr bool split = false;
     __device__ static R load(const GL bf16_t *p)
     {
-        return __uint_as_float(uint32_t(ld(reinterpret_cast<const GL uint16_t *>(p))) << 16);
+        // Converting through the __bf16 type keeps the load a plain 16-bit
+        // load followed by a shift.  Written as an integer shift, the shift
+        // can be folded into a load into the high half of a register (tied
+        // to that register's old value), which serialises the pulls.
+        return float(__builtin_bit_cast(__bf16, ld(reinterpret_cast<const GL uint16_t *>(p))));
     }
     __device__ static void store(GL bf16_t *p, R v)
     {
@@ -99,6 +106,7 @@ template <> struct Codec<bf16_t> {
 // IEEE binary16: hardware conversion (round to nearest even).
 template <> struct Codec<f16_t> {
     using R = float;
+    static constexpr bool split = false;
     __device__ static R load(const GL f16_t *p)
     {
         return float(__builtin_bit_cast(_Float16, ld(reinterpret_cast<const GL uint16_t *>(p))));
@@ -107,6 +115,34 @@ template <> struct Codec<f16_t> {
     {
         st(reinterpret_cast<GL uint16_t *>(p), __builtin_bit_cast(uint16_t, _Float16(v)));
     }
+};
+
+// Split 16-bit codecs: population q of a cell is w_q m + r_q, where m (the
+// cell's population sum, i.e. drho for the hydrodynamic lattice and eps C or
+// rho_1 for the second one) is kept in an FP32 plane and only the remainder
+// r_q -- the velocity and non-equilibrium part, orders of magnitude below
+// w_q m in low-Mach porous flow -- is rounded to 16 bits.
+struct bf16s_t { uint16_t v; };
+struct f16s_t { uint16_t v; };
+
+template <> struct Codec<bf16s_t> {
+    using R = float;
+    static constexpr bool split = true;
+    __device__ static R load(const GL bf16s_t *p)
+    {
+        return Codec<bf16_t>::load(reinterpret_cast<const GL bf16_t *>(p));
+    }
+    __device__ static void store(GL bf16s_t *p, R v) { Codec<bf16_t>::store(reinterpret_cast<GL bf16_t *>(p), v); }
+};
+
+template <> struct Codec<f16s_t> {
+    using R = float;
+    static constexpr bool split = true;
+    __device__ static R load(const GL f16s_t *p)
+    {
+        return Codec<f16_t>::load(reinterpret_cast<const GL f16_t *>(p));
+    }
+    __device__ static void store(GL f16s_t *p, R v) { Codec<f16_t>::store(reinterpret_cast<GL f16_t *>(p), v); }
 };
 
 }  // namespace plbm

@@ -70,6 +70,7 @@ struct LatDev {
     double face_rho[6], face_conc[6], face_cw[6];
     void *f[2];                 // hydrodynamic populations (deviations f - w), copies A, B
     void *h[2];                 // second lattice (solute h or fluid-1 g), copies A, B
+    void *fm[2], *hm[2];        // split 16-bit codecs: per-cell FP32 mass planes of each copy
     void *eps, *kinv, *mom, *rho1;
     double *partials, *diag;
     int *err;
@@ -224,35 +225,6 @@ __device__ inline GL T *at(GL T *p, uint32_t i)
 
 // Pull streaming (Eqs. lbe2, boltzeqD): f_q(x) = f~_q(x - v_q), or
 // f~_opp(q)(x) when x - v_q is solid (halfway bounce-back).
-template <class S, bool BB, int Q = 0>
-__device__ inline void pull_each(const void *P, uint32_t n, uint32_t idx, const Nbr &b, typename Codec<S>::R *out)
-{
-    if constexpr (BB && Q != 0) {
-        const bool s = shifted_solid<Q, -1>(b);
-        out[Q] = Codec<S>::load(at(plane<S>(P, n, s ? opp(Q) : Q), s ? idx : shifted<Q, -1>(b)));
-    } else {
-        out[Q] = Codec<S>::load(at(plane<S>(P, n, Q), shifted<Q, -1>(b)));
-    }
-    if constexpr (Q + 1 < NQ) pull_each<S, BB, Q + 1>(P, n, idx, b, out);
-}
-
-// Waves without a wall-adjacent cell (all but a thin layer) take the path
-// without bounce-back selects: uniform plane bases + 32-bit offsets only.
-template <class S>
-__device__ inline void pull_all(const void *P, uint32_t n, uint32_t idx, const Nbr &b, typename Codec<S>::R *out)
-{
-    const bool near_wall = b.sxm || b.sxp || b.sym || b.syp || b.szm || b.szp;
-    if (__builtin_amdgcn_ballot_w64(near_wall) != 0) pull_each<S, true>(P, n, idx, b, out);
-    else pull_each<S, false>(P, n, idx, b, out);
-}
-
-template <class S, int Q = 0>
-__device__ inline void store_all(void *P, uint32_t n, uint32_t idx, const typename Codec<S>::R *v)
-{
-    Codec<S>::store(at(plane_w<S>(P, n, Q), idx), v[Q]);
-    if constexpr (Q + 1 < NQ) store_all<S, Q + 1>(P, n, idx, v);
-}
-
 template <class R>
 __device__ inline R ldg(const void *base, uint32_t i)
 {
@@ -263,6 +235,94 @@ template <class R>
 __device__ inline void stg(void *base, uint32_t i, R v)
 {
     *at(static_cast<GL R *>((GL void *)base), i) = v;
+}
+
+// Split codecs: a population is w_q m + r_q, with the per-cell mass m in an
+// FP32 plane M and the remainder r_q in the 16-bit planes.
+template <class S, int Q>
+__device__ inline typename Codec<S>::R decode(const void *P, const void *M, uint32_t n, int pq, uint32_t src)
+{
+    using R = typename Codec<S>::R;
+    const R r = Codec<S>::load(at(plane<S>(P, n, pq), src));
+    if constexpr (Codec<S>::split) return fma(weight<R>(Q), ldg<R>(M, src), r);
+    else return r;
+}
+
+template <class S, bool BB, int Q = 0>
+__device__ inline void split_loads(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
+                                   typename Codec<S>::R *r, typename Codec<S>::R *m)
+{
+    using R = typename Codec<S>::R;
+    uint32_t src = shifted<Q, -1>(b);
+    int pq = Q;
+    if constexpr (BB && Q != 0) {
+        const bool s = shifted_solid<Q, -1>(b);
+        pq = s ? opp(Q) : Q;
+        src = s ? idx : src;
+    }
+    r[Q] = Codec<S>::load(at(plane<S>(P, n, pq), src));
+    m[Q] = ldg<R>(M, src);
+    if constexpr (Q + 1 < NQ) split_loads<S, BB, Q + 1>(P, M, n, idx, b, r, m);
+}
+
+template <class S, bool BB, int Q = 0>
+__device__ inline void pull_each(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
+                                 typename Codec<S>::R *out)
+{
+    using R = typename Codec<S>::R;
+    if constexpr (Codec<S>::split) {
+        // all remainder and mass loads first, then the decode
+        R r[NQ], m[NQ];
+        split_loads<S, BB>(P, M, n, idx, b, r, m);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] = fma(weight<R>(q), m[q], r[q]);
+    } else {
+        if constexpr (BB && Q != 0) {
+            const bool s = shifted_solid<Q, -1>(b);
+            out[Q] = decode<S, Q>(P, M, n, s ? opp(Q) : Q, s ? idx : shifted<Q, -1>(b));
+        } else {
+            out[Q] = decode<S, Q>(P, M, n, Q, shifted<Q, -1>(b));
+        }
+        if constexpr (Q + 1 < NQ) pull_each<S, BB, Q + 1>(P, M, n, idx, b, out);
+    }
+}
+
+// Waves without a wall-adjacent cell (all but a thin layer) take the path
+// without bounce-back selects: uniform plane bases + 32-bit offsets only.
+template <class S>
+__device__ inline void pull_all(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
+                                typename Codec<S>::R *out)
+{
+    const bool near_wall = b.sxm || b.sxp || b.sym || b.syp || b.szm || b.szp;
+    if (__builtin_amdgcn_ballot_w64(near_wall) != 0) pull_each<S, true>(P, M, n, idx, b, out);
+    else pull_each<S, false>(P, M, n, idx, b, out);
+}
+
+template <class S, int Q = 0>
+__device__ inline void store_each(void *P, uint32_t n, uint32_t idx, const typename Codec<S>::R *v)
+{
+    Codec<S>::store(at(plane_w<S>(P, n, Q), idx), v[Q]);
+    if constexpr (Q + 1 < NQ) store_each<S, Q + 1>(P, n, idx, v);
+}
+
+// Store the 19 populations of a cell (split codecs: m = sum_q v_q in FP32 and
+// the remainders v_q - w_q m in 16 bits).
+template <class S>
+__device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, const typename Codec<S>::R *v)
+{
+    using R = typename Codec<S>::R;
+    if constexpr (Codec<S>::split) {
+        R m = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) m += v[q];
+        R r[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r[q] = fma(-weight<R>(q), m, v[q]);
+        stg<R>(M, idx, m);
+        store_each<S>(P, n, idx, r);
+    } else {
+        store_each<S>(P, n, idx, v);
+    }
 }
 
 // reciprocal: the hardware approximation (1 ulp) in FP32, IEEE in FP64
@@ -566,9 +626,9 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
     if (type == CELL_FLUID) {
         const Nbr b = neighbours(L, x, y, z);
         R d[NQ];
-        pull_all<S>(L->f[src], ncell, idx, b, d);
+        pull_all<S>(L->f[src], L->fm[src], ncell, idx, b, d);
         R hq[NQ];
-        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], ncell, idx, b, hq);
+        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], L->hm[src], ncell, idx, b, hq);
 
         R drho = 0, jx = 0, jy = 0, jz = 0;
         moments_acc<R>(d, drho, jx, jy, jz);
@@ -638,16 +698,16 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
             const R omd = R(1) / R(L->tau_d);
             const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
             collide_h<R>(hq, R(1) - omd, H, vs);
-            store_all<S>(L->h[dst], ncell, idx, hq);
+            store_all<S>(L->h[dst], L->hm[dst], ncell, idx, hq);
         } else if constexpr (PHYS == PH_IMMISCIBLE) {
             R g[NQ];
             const R rec = Fn > R(0) ? R(L->beta) * C * (R(1) - C) * rho * iFn : R(0);
             const R Cw[3] = {C * weight<R>(0), C * weight<R>(1), C * weight<R>(7)};
             const R rw[3] = {R(0), rec * weight<R>(1), rec * weight<R>(7) * R(0.70710678118654752440)};
             recolour<R>(g, d, C, Cw, rw, F);
-            store_all<S>(L->h[dst], ncell, idx, g);
+            store_all<S>(L->h[dst], L->hm[dst], ncell, idx, g);
         }
-        store_all<S>(L->f[dst], ncell, idx, d);
+        store_all<S>(L->f[dst], L->fm[dst], ncell, idx, d);
 
         if (mom) {
             void *M = L->mom;
@@ -705,7 +765,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
     } else {
         const Nbr b = neighbours(L, x, y, z);
         R g[NQ];
-        pull_all<S>(L->h[src], ncell, idx, b, g);
+        pull_all<S>(L->h[src], L->hm[src], ncell, idx, b, g);
         v = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v += g[q];
@@ -863,8 +923,8 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
         mC = C;
     }
     for (int cpy = 0; cpy < 2; ++cpy) {
-        store_all<S>(L->f[cpy], ncell, idx, d);
-        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], ncell, idx, hq);
+        store_all<S>(L->f[cpy], L->fm[cpy], ncell, idx, d);
+        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], L->hm[cpy], ncell, idx, hq);
     }
     void *M = L->mom;
     stg<R>(M, idx, mrho);
@@ -909,8 +969,12 @@ __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, in
     const uint32_t ncell = L->ncell;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= ncell) return;
+    using R = typename Codec<S>::R;
     const void *P = which == 0 ? L->f[src] : L->h[src];
-    for (int q = 0; q < NQ; ++q) dst[size_t(q) * ncell + idx] = Codec<S>::load(at(plane<S>(P, ncell, q), idx));
+    const void *M = which == 0 ? L->fm[src] : L->hm[src];
+    const R m = Codec<S>::split ? ldg<R>(M, idx) : R(0);
+    for (int q = 0; q < NQ; ++q)
+        dst[size_t(q) * ncell + idx] = fma(weight<R>(q), m, Codec<S>::load(at(plane<S>(P, ncell, q), idx)));
 }
 
 }  // namespace plbm

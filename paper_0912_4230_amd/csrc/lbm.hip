@@ -32,8 +32,10 @@ size_t storage_bytes(int storage)
 size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 struct Layout {
-    size_t lat, err, diag, partials, eps, kinv, mom, rho1, f0, f1, h0, h1, total;
+    size_t lat, err, diag, partials, eps, kinv, mom, rho1, f0, f1, h0, h1, fm0, fm1, hm0, hm1, total;
 };
+
+bool split_storage(int storage) { return storage == LBM_BF16_SPLIT || storage == LBM_F16_SPLIT; }
 
 bool is_fin(double v) { return isfinite(v) != 0; }
 
@@ -45,7 +47,7 @@ bool valid_desc(const lbm_desc *d)
     const long long ncell = (long long)d->nx * d->ny * d->nz;
     if (ncell > (1LL << 31) - BLOCK) return false;
     if (d->physics < LBM_SINGLE || d->physics > LBM_IMMISCIBLE) return false;
-    if (d->storage < LBM_F64 || d->storage > LBM_F16_DEV) return false;
+    if (d->storage < LBM_F64 || d->storage > LBM_F16_SPLIT) return false;
     const int n[3] = {d->nx, d->ny, d->nz};
     for (int a = 0; a < 3; ++a) {
         const int k0 = d->face[2 * a].kind, k1 = d->face[2 * a + 1].kind;
@@ -96,6 +98,11 @@ Layout layout(const lbm_desc *d)
     L.f1 = o;        o = align_up(o + NQ * n * sb);
     L.h0 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * n * sb);
     L.h1 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * n * sb);
+    const bool sp = split_storage(d->storage), two = d->physics != LBM_SINGLE;
+    L.fm0 = o;       if (sp) o = align_up(o + n * sizeof(float));
+    L.fm1 = o;       if (sp) o = align_up(o + n * sizeof(float));
+    L.hm0 = o;       if (sp && two) o = align_up(o + n * sizeof(float));
+    L.hm1 = o;       if (sp && two) o = align_up(o + n * sizeof(float));
     L.total = o;
     return L;
 }
@@ -149,7 +156,9 @@ Launch step_for_storage(int storage)
     case LBM_F64: return launch_step<P, double>;
     case LBM_F32: return launch_step<P, float>;
     case LBM_BF16_DEV: return launch_step<P, bf16_t>;
-    default: return launch_step<P, f16_t>;
+    case LBM_F16_DEV: return launch_step<P, f16_t>;
+    case LBM_BF16_SPLIT: return launch_step<P, bf16s_t>;
+    default: return launch_step<P, f16s_t>;
     }
 }
 
@@ -168,7 +177,9 @@ Launch colour_launcher(int storage)
     case LBM_F64: return launch_colour<double>;
     case LBM_F32: return launch_colour<float>;
     case LBM_BF16_DEV: return launch_colour<bf16_t>;
-    default: return launch_colour<f16_t>;
+    case LBM_F16_DEV: return launch_colour<f16_t>;
+    case LBM_BF16_SPLIT: return launch_colour<bf16s_t>;
+    default: return launch_colour<f16s_t>;
     }
 }
 
@@ -195,7 +206,9 @@ void init_for_storage(const lbm_sim *h, const lbm_medium *m, int blocks)
     case LBM_F64: launch_init<P, double>(h, m, blocks); break;
     case LBM_F32: launch_init<P, float>(h, m, blocks); break;
     case LBM_BF16_DEV: launch_init<P, bf16_t>(h, m, blocks); break;
-    default: launch_init<P, f16_t>(h, m, blocks); break;
+    case LBM_F16_DEV: launch_init<P, f16_t>(h, m, blocks); break;
+    case LBM_BF16_SPLIT: launch_init<P, bf16s_t>(h, m, blocks); break;
+    default: launch_init<P, f16s_t>(h, m, blocks); break;
     }
 }
 
@@ -318,6 +331,11 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     D.f[1] = w + L.f1;
     D.h[0] = d->physics != LBM_SINGLE ? w + L.h0 : nullptr;
     D.h[1] = d->physics != LBM_SINGLE ? w + L.h1 : nullptr;
+    const bool sp = split_storage(d->storage), two = d->physics != LBM_SINGLE;
+    D.fm[0] = sp ? w + L.fm0 : nullptr;
+    D.fm[1] = sp ? w + L.fm1 : nullptr;
+    D.hm[0] = sp && two ? w + L.hm0 : nullptr;
+    D.hm[1] = sp && two ? w + L.hm1 : nullptr;
     D.eps = w + L.eps;
     D.kinv = w + L.kinv;
     D.mom = w + L.mom;
@@ -466,8 +484,14 @@ lbm_status lbm_populations(lbm_t h, int lattice, void *dst)
     case LBM_BF16_DEV:
         hipLaunchKernelGGL(k_export<bf16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
         break;
-    default:
+    case LBM_F16_DEV:
         hipLaunchKernelGGL(k_export<f16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
+        break;
+    case LBM_BF16_SPLIT:
+        hipLaunchKernelGGL(k_export<bf16s_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
+        break;
+    default:
+        hipLaunchKernelGGL(k_export<f16s_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, lattice, h->cur, static_cast<float *>(dst));
         break;
     }
     lbm_status st;

@@ -111,7 +111,7 @@ def crop_oracle():
     return p, r, mask
 
 
-@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("storage", ["bf16", "f16", "bf16s", "f16s"])
 def test_precision_form_crop_vs_oracle(storage, crop_oracle):
     """The 512^3 precision-form physics on the 64^3 crop [0,64)^3 of the same
     seeded medium (own reservoirs at x = 0 and 63), 2000 steps, 16-bit storage
@@ -133,7 +133,9 @@ def test_precision_form_crop_vs_oracle(storage, crop_oracle):
     # FP16 rho 3.3e-4, drho 0.035, V' 0.066, C 4.2e-3; FP32 rho 2.0e-7,
     # drho 2.0e-5, V' 3.4e-5, C 2.0e-5
     bounds = {"bf16": {"rho": 5e-3, "drho": 0.5, "vel": 1.0, "conc": 0.25},
-              "f16": {"rho": 5e-4, "drho": 0.05, "vel": 0.1, "conc": 1e-2}}[storage]
+              "f16": {"rho": 5e-4, "drho": 0.05, "vel": 0.1, "conc": 1e-2},
+              "bf16s": {"rho": 3e-3, "drho": 0.3, "vel": 0.5, "conc": 5e-4},
+              "f16s": {"rho": 2e-5, "drho": 3e-3, "vel": 3e-2, "conc": 5e-4}}[storage]
     for k, b in bounds.items():
         assert e[k] < b, (k, e[k])
     f = out["f32"]

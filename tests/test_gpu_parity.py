@@ -81,7 +81,7 @@ def test_two_fluid_drop_ragged(storage, tol):
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
-@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("storage", ["bf16", "f16", "bf16s", "f16s"])
 def test_reduced_precision_storage_errors(storage):
     """16-bit population storage with FP32 compute: errors against the FP64
     oracle, stated per field (bounds chosen from measurement)."""
@@ -93,7 +93,8 @@ def test_reduced_precision_storage_errors(storage):
     g, r, mask, dg, od = run_pair(p, 120, storage)
     e = errors(g, r, mask)
     report(f"miscible 37x29x23 x120 {storage}", e)
-    bounds = {"bf16": {"rho": 1e-3, "conc": 2e-2}, "f16": {"rho": 2e-4, "conc": 5e-3}}[storage]
+    bounds = {"bf16": {"rho": 1e-3, "conc": 2e-2}, "f16": {"rho": 2e-4, "conc": 5e-3},
+              "bf16s": {"rho": 1e-4, "conc": 2e-3}, "f16s": {"rho": 1e-5, "conc": 3e-4}}[storage]
     assert e["rho"] < bounds["rho"] and e["conc"] < bounds["conc"]
     assert np.isfinite(e["vel"])
 
@@ -166,7 +167,8 @@ def test_conservation_periodic_gpu():
     # (mass, solute) bounds over 300 steps.  FP64 is exact to round-off; the
     # hydrodynamic lattice is stored as deviations, so its FP32 drift is far
     # below the solute's, which is stored as is (measured FP32: 8e-12, 7e-6).
-    tols = {"f64": (1e-13, 1e-12), "f32": (1e-9, 3e-5), "bf16": (1e-2, 5e-2), "f16": (1e-3, 1e-2)}
+    tols = {"f64": (1e-13, 1e-12), "f32": (1e-9, 3e-5), "bf16": (1e-2, 5e-2), "f16": (1e-3, 1e-2),
+            "bf16s": (1e-5, 1e-4), "f16s": (1e-5, 1e-4)}
     for storage, (tm, ts) in tols.items():
         p = I.miscible(shape=(24, 20, 16), seed=2, reservoirs=False)
         p.G = (1e-5, 2e-6, 0.0)
