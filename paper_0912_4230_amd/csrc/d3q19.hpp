@@ -91,11 +91,7 @@ template <> struct Codec<bf16_t> {
     static constexpr bool split = false;
     __device__ static R load(const GL bf16_t *p)
     {
-        // Converting through the __bf16 type keeps the load a plain 16-bit
-        // load followed by a shift.  Written as an integer shift, the shift
-        // can be folded into a load into the high half of a register (tied
-        // to that register's old value), which serialises the pulls.
-        return float(__builtin_bit_cast(__bf16, ld(reinterpret_cast<const GL uint16_t *>(p))));
+        return __uint_as_float(uint32_t(ld(reinterpret_cast<const GL uint16_t *>(p))) << 16);
     }
     __device__ static void store(GL bf16_t *p, R v)
     {
@@ -130,7 +126,11 @@ template <> struct Codec<bf16s_t> {
     static constexpr bool split = true;
     __device__ static R load(const GL bf16s_t *p)
     {
-        return Codec<bf16_t>::load(reinterpret_cast<const GL bf16_t *>(p));
+        // Converting through the __bf16 type keeps this a plain 16-bit load
+        // followed by a shift.  Written as an integer shift, the shift can be
+        // folded into a load into the high half of a register (tied to that
+        // register's old value), which serialised the split pulls.
+        return float(__builtin_bit_cast(__bf16, ld(reinterpret_cast<const GL uint16_t *>(p))));
     }
     __device__ static void store(GL bf16s_t *p, R v) { Codec<bf16_t>::store(reinterpret_cast<GL bf16_t *>(p), v); }
 };

@@ -74,6 +74,7 @@ struct LatDev {
     void *eps, *kinv, *mom, *rho1;
     double *partials, *diag;
     int *err;
+    uint32_t div_nx[3], div_nxy[3];   // magic numbers of the divisions by nx and nx*ny
 };
 
 // Arguments of one batched launch: lattice l owns logical blocks
@@ -325,9 +326,26 @@ __device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, con
     }
 }
 
-// reciprocal: the hardware approximation (1 ulp) in FP32, IEEE in FP64
+// reciprocal, square root, reciprocal square root and exponential: the
+// hardware instructions (about 1 ulp) in FP32, the correctly rounded / libm
+// forms in FP64
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp(double x) { return 1.0 / x; }
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double fsqrt(double x) { return sqrt(x); }
+__device__ inline float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double frsq(double x) { return 1.0 / sqrt(x); }
+__device__ inline float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ inline double fexp(double x) { return exp(x); }
+
+// unsigned division by an invariant divisor (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", 1994): the host
+// precomputes g = (m, s1, s2); exact for every 32-bit dividend.
+__device__ inline uint32_t udiv(uint32_t n, const uint32_t g[3])
+{
+    const uint32_t t = __umulhi(g[0], n);
+    return (t + ((n - t) >> g[1])) >> g[2];
+}
 
 // grad(eps) (times eps) by sum_q w_q eps(x + v_q) v_q; a solid neighbour
 // takes eps(x).  The caller scales by 3 / eps(x).
@@ -363,9 +381,13 @@ template <> struct Newton<double> { static constexpr double tol = 1e-15; };
 template <class R>
 __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], const R ilam[3])
 {
-    R s = sqrt((W[0] * ilam[0]) * (W[0] * ilam[0]) + (W[1] * ilam[1]) * (W[1] * ilam[1]) +
-               (W[2] * ilam[2]) * (W[2] * ilam[2]));
-    if (s > R(0)) {
+    R s = fsqrt((W[0] * ilam[0]) * (W[0] * ilam[0]) + (W[1] * ilam[1]) * (W[1] * ilam[1]) +
+                (W[2] * ilam[2]) * (W[2] * ilam[2]));
+    // the root lies in [s / (1 + max mu s / min lam), s]: when that bracket is
+    // below the working precision the Darcy value is the answer
+    const R mumax = fmax(mu[0], fmax(mu[1], mu[2]));
+    const R lmin = fmin(lam[0], fmin(lam[1], lam[2]));
+    if (s > R(0) && mumax * s > Newton<R>::tol * lmin) {
         for (int it = 0; it < 8; ++it) {
             R R2 = 0, dR = 0;
 #pragma unroll
@@ -387,16 +409,20 @@ __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], con
     return s;
 }
 
-// Moments after streaming; populations in deviation form.
-template <class R, int Q = 0>
+// Moments after streaming; populations in deviation form.  Directions come
+// in opposite pairs (q, q+1), q odd: their sum feeds the density, their
+// difference the momentum.
+template <class R, int P = 0>
 __device__ inline void moments_acc(const R *d, R &drho, R &jx, R &jy, R &jz)
 {
-    const R v = d[Q];
-    drho += v;
-    if (cx(Q)) jx += cx(Q) > 0 ? v : -v;
-    if (cy(Q)) jy += cy(Q) > 0 ? v : -v;
-    if (cz(Q)) jz += cz(Q) > 0 ? v : -v;
-    if constexpr (Q + 1 < NQ) moments_acc<R, Q + 1>(d, drho, jx, jy, jz);
+    constexpr int q = 2 * P + 1;
+    if constexpr (P == 0) drho += d[0];
+    const R s = d[q] + d[q + 1], t = d[q] - d[q + 1];
+    drho += s;
+    if (cx(q)) jx += cx(q) > 0 ? t : -t;
+    if (cy(q)) jy += cy(q) > 0 ? t : -t;
+    if (cz(q)) jz += cz(q) > 0 ? t : -t;
+    if constexpr (P + 1 < (NQ - 1) / 2) moments_acc<R, P + 1>(d, drho, jx, jy, jz);
 }
 
 template <class R, int Q>
@@ -458,53 +484,53 @@ __device__ inline Coll<R> make_coll(R drho, R rho, R omega, R ie, const R u[3], 
     return c;
 }
 
-template <class R, bool ST, int Q = 0>
+// Directions q (odd) and q+1 are opposite: with S = v.a + v.b and
+// P = (v.u)(k45 v.a + k9 v.b) - K0 computed once, X_q = P + 3 S and
+// X_{q+1} = P - 3 S (all dot products change sign, the quadratic term not).
+template <class R, bool ST, int P = 0>
 __device__ inline void collide_f(R *d, const Coll<R> &c)
 {
-    constexpr int k = Q == 0 ? 0 : (Q <= 6 ? 1 : 2);
-    R v;
-    if constexpr (Q == 0) {
-        v = c.base[0] - c.wr[0] * c.K0;
-    } else {
-        const R cu = cdot<R, Q>(c.u), ca = cdot<R, Q>(c.a), cb = cdot<R, Q>(c.b);
-        const R X = fma(R(3), ca + cb, fma(cu, fma(c.k45, ca, c.k9 * cb), -c.K0));
-        v = fma(c.wr[k], X, c.base[k]);
-        if constexpr (ST) {
-            const R cG = cdot<R, Q>(c.F);
-            v = fma(c.s1[k] * cG, cG, v);
-        }
+    constexpr int q = 2 * P + 1, k = q <= 6 ? 1 : 2;
+    if constexpr (P == 0) d[0] = fma(c.om1, d[0], c.base[0] - c.wr[0] * c.K0);
+    const R cu = cdot<R, q>(c.u), ca = cdot<R, q>(c.a), cb = cdot<R, q>(c.b);
+    const R S = ca + cb;
+    const R Pq = fma(cu, fma(c.k45, ca, c.k9 * cb), -c.K0);
+    R vq = fma(c.wr[k], fma(R(3), S, Pq), c.base[k]);
+    R vo = fma(c.wr[k], fma(R(-3), S, Pq), c.base[k]);
+    if constexpr (ST) {
+        const R cG = cdot<R, q>(c.F);
+        const R t = c.s1[k] * cG;
+        vq = fma(t, cG, vq);
+        vo = fma(t, cG, vo);
     }
-    d[Q] = fma(c.om1, d[Q], v);
-    if constexpr (Q + 1 < NQ) collide_f<R, ST, Q + 1>(d, c);
+    d[q] = fma(c.om1, d[q], vq);
+    d[q + 1] = fma(c.om1, d[q + 1], vo);
+    if constexpr (P + 1 < (NQ - 1) / 2) collide_f<R, ST, P + 1>(d, c);
 }
 
 // Solute BGK (Eqs. equild, boltzeqD):
-// h' = (1 - omega_D) h + omega_D w eps C (1 + 3 v.V*).
-template <class R, int Q = 0>
+// h' = (1 - omega_D) h + omega_D w eps C (1 + 3 v.V*), opposite pairs together.
+template <class R, int P = 0>
 __device__ inline void collide_h(R *h, R om1d, const R H[3], const R vs[3])
 {
-    constexpr int k = Q == 0 ? 0 : (Q <= 6 ? 1 : 2);
-    if constexpr (Q == 0) {
-        h[Q] = fma(om1d, h[Q], H[0]);
-    } else {
-        const R cv = cdot<R, Q>(vs);
-        h[Q] = fma(om1d, h[Q], fma(R(3) * H[k], cv, H[k]));
-    }
-    if constexpr (Q + 1 < NQ) collide_h<R, Q + 1>(h, om1d, H, vs);
+    constexpr int q = 2 * P + 1, k = q <= 6 ? 1 : 2;
+    if constexpr (P == 0) h[0] = fma(om1d, h[0], H[0]);
+    const R t = R(3) * H[k] * cdot<R, q>(vs);
+    h[q] = fma(om1d, h[q], H[k] + t);
+    h[q + 1] = fma(om1d, h[q + 1], H[k] - t);
+    if constexpr (P + 1 < (NQ - 1) / 2) collide_h<R, P + 1>(h, om1d, H, vs);
 }
 
 // Two-fluid recolouring: g' = C f' + beta C (1 - C) rho w cos(v, F).
-template <class R, int Q = 0>
+template <class R, int P = 0>
 __device__ inline void recolour(R *g, const R *d, R C, const R Cw[3], const R rw[3], const R F[3])
 {
-    constexpr int k = Q == 0 ? 0 : (Q <= 6 ? 1 : 2);
-    if constexpr (Q == 0) {
-        g[Q] = fma(C, d[Q], Cw[0]);
-    } else {
-        const R cG = cdot<R, Q>(F);
-        g[Q] = fma(rw[k], cG, fma(C, d[Q], Cw[k]));
-    }
-    if constexpr (Q + 1 < NQ) recolour<R, Q + 1>(g, d, C, Cw, rw, F);
+    constexpr int q = 2 * P + 1, k = q <= 6 ? 1 : 2;
+    if constexpr (P == 0) g[0] = fma(C, d[0], Cw[0]);
+    const R t = rw[k] * cdot<R, q>(F);
+    g[q] = fma(C, d[q], Cw[k]) + t;
+    g[q + 1] = fma(C, d[q + 1], Cw[k]) - t;
+    if constexpr (P + 1 < (NQ - 1) / 2) recolour<R, P + 1>(g, d, C, Cw, rw, F);
 }
 
 // Porous velocity and force (Eqs. forcement, expandV, expandVsub with eps on
@@ -516,13 +542,13 @@ __device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R n
     R W[3], lam[3], ilam[3], mu[3], sk[3];
     R Feps = R(0);
     const bool forch = L->forch != 0;
-    if (forch) Feps = R(1.75) / sqrt(R(150) * eps * eps * eps);
+    if (forch) Feps = R(1.75) * frsq(R(150) * eps * eps * eps);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         W[a] = V[a] + R(0.5) * eps * G[a];
         lam[a] = R(1) + R(0.5) * eps * nu * kinv[a];
         ilam[a] = rcp(lam[a]);
-        sk[a] = forch ? sqrt(kinv[a]) : R(0);
+        sk[a] = forch ? fsqrt(kinv[a]) : R(0);
         mu[a] = R(0.5) * eps * Feps * sk[a];
     }
     if (forch) {
@@ -533,7 +559,7 @@ __device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R n
 #pragma unroll
         for (int a = 0; a < 3; ++a) u[a] = W[a] * ilam[a];
     }
-    const R sp = forch ? sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) : R(0);
+    const R sp = forch ? fsqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) : R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         Fx[a] = eps * G[a] - eps * nu * kinv[a] * u[a] - eps * Feps * sp * sk[a] * u[a];
@@ -617,9 +643,9 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
     int type = CELL_SOLID;
     int x = 0, y = 0, z = 0, face = -1;
     if (idx < ncell) {
-        z = idx / nxy;
+        z = udiv(idx, L->div_nxy);
         const uint32_t r = idx - uint32_t(z) * nxy;
-        y = r / nx;
+        y = udiv(r, L->div_nx);
         x = r - uint32_t(y) * nx;
         type = cell_type(L, x, y, z, face);
     }
@@ -663,9 +689,9 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
         if constexpr (PHYS == PH_IMMISCIBLE) {
             nu = C * R(L->nu1) + (R(1) - C) * R(L->nu2);
         } else if constexpr (PHYS == PH_MISCIBLE) {
-            nu = nuc * exp(R(L->k1) * C + R(L->k0));
+            nu = nuc * fexp(R(L->k1) * C + R(L->k0));
         } else {
-            nu = nuc * exp(R(L->k0));
+            nu = nuc * fexp(R(L->k0));
         }
         const R tau = R(0.5) + R(3) * nu;
         const R omega = rcp(tau);
@@ -751,9 +777,9 @@ __global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
     const uint32_t idx = uint32_t(lb) * BLOCK + threadIdx.x;
     if (idx >= ncell) return;
     const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
-    const int z = idx / nxy;
+    const int z = udiv(idx, L->div_nxy);
     const uint32_t r = idx - uint32_t(z) * nxy;
-    const int y = r / nx;
+    const int y = udiv(r, L->div_nx);
     const int x = r - uint32_t(y) * nx;
     int face;
     const int type = cell_type(L, x, y, z, face);

@@ -107,6 +107,19 @@ Layout layout(const lbm_desc *d)
     return L;
 }
 
+// (m, s1, s2) of the division by d >= 1 (Granlund and Montgomery 1994):
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0); then n / d = (t + ((n - t) >> s1)) >> s2, t = mulhi(m, n).
+void magic_divisor(uint32_t d, uint32_t g[3])
+{
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+    g[0] = uint32_t(m);
+    g[1] = l < 1 ? l : 1;
+    g[2] = l > 0 ? l - 1 : 0;
+}
+
 double time_factor(const lbm_desc *d, double t)
 {
     double tf = d->a0 + d->a1 * exp(d->alpha * t);
@@ -302,6 +315,8 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
         const size_t bpp = plane_cells / BLOCK;
         D.bpp = (PLBM_SLAB && plane_cells % BLOCK == 0 && bpp % 8 == 0) ? int(bpp) : 0;
     }
+    magic_divisor(uint32_t(d->nx), D.div_nx);
+    magic_divisor(uint32_t(d->nx) * uint32_t(d->ny), D.div_nxy);
     D.physics = d->physics;
     D.forch = d->forchheimer ? 1 : 0;
     D.eps_grad = d->eps_gradient ? 1 : 0;
