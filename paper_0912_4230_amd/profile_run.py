@@ -63,7 +63,7 @@ def main():
     s = sub.add_parser("step")
     s.add_argument("--physics", default="miscible", choices=["single", "miscible", "immiscible"])
     s.add_argument("--size", type=int, default=256)
-    s.add_argument("--storage", default="f32", choices=["f64", "f32", "bf16", "f16"])
+    s.add_argument("--storage", default="f32", choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s"])
     s.add_argument("--steps", type=int, default=10)
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=2048)
