@@ -43,7 +43,8 @@
  *    colour field rho_1 = Sum g, C = rho_1 / rho, nu = C nu_1 + (1-C) nu_2,
  *    recolouring g~_i = C f~_i + beta C (1-C) rho w_i cos(v_i, F);
  *  - walls: halfway bounce-back; reservoirs: cells held at the equilibrium
- *    of (rho_bc, V' = 0, C_bc).
+ *    of (rho_bc, V' = 0, C_bc); the cells of an optional obstacle mask are
+ *    solid like wall cells, with their own contact angle.
  *  - populations of the hydrodynamic lattice are held as deviations
  *    d_i = f_i - w_i (an exact change of variable) so that the round-off of
  *    the moments scales with the deviations and not with 1.
@@ -111,6 +112,7 @@ typedef struct {
     double A, beta;     /* surface-tension strength, recolouring strength */
     int face_kind[6];   /* -x,+x,-y,+y,-z,+z : FACE_* */
     double face_rho[6], face_conc[6], face_angle[6];  /* reservoir rho, C; wall angle (deg) */
+    double solid_angle; /* contact angle (deg) of the obstacle cells of a solid mask */
 } orc_params;
 
 typedef struct {
@@ -146,7 +148,10 @@ static long neighbour(const orc_state *s, int x, int y, int z, int dx, int dy, i
     return cidx(s, c[0], c[1], c[2]);
 }
 
-static void classify(orc_state *s)
+/* Cell classes: a cell on a wall face is solid; otherwise a cell marked in
+ * the optional obstacle mask is solid (its wall index is 6); otherwise a
+ * cell on a reservoir face belongs to that reservoir; all others are fluid. */
+static void classify(orc_state *s, const unsigned char *solid)
 {
     int n[3] = {s->p.nx, s->p.ny, s->p.nz};
     for (int z = 0; z < n[2]; ++z)
@@ -159,6 +164,7 @@ static void classify(orc_state *s)
                     int a = f / 2, pos = (f % 2) ? n[a] - 1 : 0;
                     if (s->p.face_kind[f] == FACE_WALL && c[a] == pos) { t = CELL_SOLID; tf = (unsigned char)f; }
                 }
+                if (t == CELL_FLUID && solid && solid[i]) { t = CELL_SOLID; tf = 6; }
                 for (int f = 0; f < 6 && t == CELL_FLUID; ++f) {
                     int a = f / 2, pos = (f % 2) ? n[a] - 1 : 0;
                     if (s->p.face_kind[f] == FACE_RESERVOIR && c[a] == pos) { t = CELL_RESERVOIR; tf = (unsigned char)f; }
@@ -168,11 +174,13 @@ static void classify(orc_state *s)
             }
 }
 
-/* wall colour C_w = (1 + cos theta)/2 of wall face f (reference density 1). */
+/* wall colour C_w = (1 + cos theta)/2 of wall face f, or of the obstacle
+ * cells for f = 6 (reference density 1). */
 static double wall_colour(const orc_state *s, int f)
 {
     const double pi = 3.14159265358979323846;
-    return 0.5 * (1.0 + cos(s->p.face_angle[f] * pi / 180.0));
+    const double th = f == 6 ? s->p.solid_angle : s->p.face_angle[f];
+    return 0.5 * (1.0 + cos(th * pi / 180.0));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -503,9 +511,12 @@ void orc_destroy(orc_state *s)
 /* Create the state and apply the initial conditions (flowchart, first three
  * boxes): f = f^eq(rho0, V' := V0, F, eps, tau(C0, 0)); h = h^eq(eps C0,
  * V0 + D grad(eps)/eps); g = C0 f.  Arrays are FP64, idx = x + nx (y + ny z);
- * kinv and vel0 hold 3 planes.  Returns NULL on allocation failure.        */
+ * kinv and vel0 hold 3 planes; solid (may be NULL) marks obstacle cells,
+ * which carry no state and reflect the populations that stream into them.
+ * Returns NULL on allocation failure.                                      */
 orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv,
-                      const double *rho0, const double *vel0, const double *c0)
+                      const double *rho0, const double *vel0, const double *c0,
+                      const unsigned char *solid)
 {
     lattice_setup();
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
@@ -528,7 +539,7 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
         !s->vel || !s->conc || !s->vsnap || !s->rho1) { orc_destroy(s); return NULL; }
     memcpy(s->eps, eps, sizeof(double) * n);
     memcpy(s->kinv, kinv, sizeof(double) * 3 * n);
-    classify(s);
+    classify(s, solid);
     s->cur = 0;
 
     /* initial moments */

@@ -30,6 +30,7 @@ class OrcParams(C.Structure):
         ("A", C.c_double), ("beta", C.c_double),
         ("face_kind", C.c_int * 6),
         ("face_rho", C.c_double * 6), ("face_conc", C.c_double * 6), ("face_angle", C.c_double * 6),
+        ("solid_angle", C.c_double),
     ]
 
 
@@ -42,7 +43,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)
         L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.POINTER(OrcParams), dp, dp, dp, dp, dp]
+        L.orc_create.argtypes = [C.POINTER(OrcParams), dp, dp, dp, dp, dp, C.POINTER(C.c_ubyte)]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_int]
         L.orc_step.restype = C.c_int
@@ -91,6 +92,7 @@ def params_from_problem(p) -> OrcParams:
     o.face_rho = (C.c_double * 6)(*[float(f.rho) for f in p.faces])
     o.face_conc = (C.c_double * 6)(*[float(f.conc) for f in p.faces])
     o.face_angle = (C.c_double * 6)(*[float(f.angle) for f in p.faces])
+    o.solid_angle = float(p.solid_angle)
     return o
 
 
@@ -151,7 +153,11 @@ class Oracle:
         self._keep = [_vec(p.eps).reshape(-1), _vec(p.kinv).reshape(-1), _vec(p.rho0).reshape(-1),
                       _vec(p.vel0).reshape(-1), _vec(p.c0).reshape(-1)]
         self.params = params_from_problem(p)
-        h = lib().orc_create(C.byref(self.params), *[_dp(a) for a in self._keep])
+        solid = None
+        if p.solid is not None:
+            solid = np.ascontiguousarray(np.asarray(p.solid).reshape(-1) != 0, dtype=np.uint8)
+        sp = solid.ctypes.data_as(C.POINTER(C.c_ubyte)) if solid is not None else None
+        h = lib().orc_create(C.byref(self.params), *[_dp(a) for a in self._keep], sp)
         if not h:
             raise MemoryError("oracle allocation failed")
         self.h = C.c_void_p(h)

@@ -61,6 +61,8 @@ class Problem:
     rho0: Optional[np.ndarray] = None   # (nz,ny,nx)
     vel0: Optional[np.ndarray] = None   # (3,nz,ny,nx)
     c0: Optional[np.ndarray] = None     # (nz,ny,nx)
+    solid: Optional[np.ndarray] = None  # (nz,ny,nx) nonzero = obstacle cell (no state, bounce-back)
+    solid_angle: float = 90.0           # contact angle of the obstacle surfaces (two-fluid model)
 
     @property
     def ncell(self) -> int:
@@ -230,6 +232,44 @@ def drop(shape=(128, 128, 128), radius=20.0, centre=None, speed=0.05, tau1=0.7, 
         faces[5] = Face(kind=WALL, angle=top_angle)
     p = Problem(shape=tuple(shape), physics=IMMISCIBLE, tau1=tau1, tau2=tau2, A=A, beta=beta,
                 faces=faces, c0=c0, vel0=vel0)
+    return p.fill_defaults()
+
+
+def sphere_obstacles(shape, seed: int = 0, solid_fraction: float = 0.1, radius=(2.0, 4.0),
+                     keep_planes=(0,)) -> np.ndarray:
+    """Seeded obstacle mask: spheres with radii uniform in `radius` and centres
+    uniform in the box (distances wrap on every axis), added until the solid
+    fraction reaches `solid_fraction`.  The planes x = i for i in
+    `keep_planes` (and x = nx-1-i) stay free so that reservoir faces on x keep
+    a fluid layer next to them.  Returns uint8 (nz,ny,nx)."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    mask = np.zeros((nz, ny, nx), dtype=bool)
+    ncell = nx * ny * nz
+    while mask.sum() < solid_fraction * ncell:
+        c = rng.random(3) * np.array([nx, ny, nz])
+        r = rng.uniform(*radius)
+        d = [np.abs(a - ca) for a, ca in zip((x, y, z), c)]
+        d = [np.minimum(da, n - da) for da, n in zip(d, (nx, ny, nz))]
+        mask |= d[0] ** 2 + d[1] ** 2 + d[2] ** 2 <= r * r
+    for i in keep_planes:
+        for xi in sorted({i, 1 + i, nx - 1 - i, nx - 2 - i}):
+            if 0 <= xi < nx:
+                mask[:, :, xi] = False
+    return mask.astype(np.uint8)
+
+
+def duct(shape=(4, 20, 20), G=1e-6, tau=0.8) -> Problem:
+    """Body-force driven flow along x through a square duct made of obstacle
+    cells: the y and z edge layers of the box are solid, every face is
+    periodic, free fluid inside (eps = 1, K^-1 = 0)."""
+    nx, ny, nz = shape
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    solid[:, [0, ny - 1], :] = 1
+    solid[[0, nz - 1], :, :] = 1
+    p = Problem(shape=tuple(shape), physics=SINGLE, G=(G, 0.0, 0.0), nu0=(tau - 0.5) / 3.0,
+                solid=solid)
     return p.fill_defaults()
 
 
