@@ -16,7 +16,8 @@
  *     surface-tension term of Eqs. equilc1/2 (tensor of Eq. eqsurftens);
  *   - walls (halfway bounce-back, with a wall colour that sets the contact
  *     angle in two-fluid mode), fixed-state reservoirs (pressure inlet /
- *     outlet) and periodic faces (Sec. 4, boundary conditions).
+ *     outlet) and periodic faces (Sec. 4, boundary conditions), and optional
+ *     obstacle cells anywhere in the box given by a per-cell mask.
  *
  * One time step follows the simulation procedure of Sec. 4 (flowchart):
  * stream both lattices, take the moments, form the colour gradient, collide.
@@ -114,6 +115,11 @@ typedef struct {
     lbm_face face[6];           /* order: -x, +x, -y, +y, -z, +z */
     int diag_every;             /* FP64 diagnostics every k steps (0: only at the end
                                    of each lbm_step call) */
+    int solid_mask;             /* 1: lbm_set_medium takes a per-cell obstacle mask
+                                   (lbm_medium.solid); the workspace then holds one
+                                   32-bit link word per cell */
+    double solid_contact_angle_deg;  /* two-fluid: contact angle of fluid 1 on the
+                                   obstacle cells of the mask */
 } lbm_desc;
 
 /* Medium and initial fields (flowchart of Sec. 4: set rho, V, C, the
@@ -129,7 +135,17 @@ typedef struct {
     const void *c0;             /* ncell initial concentrations; NULL: 0 */
     double eps_uniform;
     double kinv_uniform[3];
+    const unsigned char *solid; /* ncell bytes, nonzero = obstacle cell; only with
+                                   desc.solid_mask = 1 (NULL there: no obstacles) */
 } lbm_medium;
+/* Obstacle cells of the mask are solid exactly like the cells of a wall face
+ * (Sec. 4: bounce-back on every link into them, no state, moments read 0);
+ * a cell on a wall face is a wall cell, else a masked cell is an obstacle,
+ * else a cell on a reservoir face belongs to the reservoir.  Their porosity
+ * and permeability values are ignored; in the porosity gradient a solid
+ * neighbour takes the porosity of the cell itself.  The link word of a cell
+ * holds bit 0 = the cell is solid and bit q = the cell x - v_q is solid (q in
+ * the order of lbm_lattice), built once by lbm_set_medium. */
 
 typedef struct lbm_sim *lbm_t;
 
@@ -146,9 +162,10 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes,
 
 /* Copy the medium and the initial fields in and set the populations to their
  * equilibria (Eqs. equilc1/2, equild; two-fluid: g = C f).  Validates the
- * fields on the device (eps in (0,1], K^-1 >= 0, rho0 > 0, all finite) and
- * returns LBM_EINVAL if a value is out of range.  Resets the step count.
- * Synchronises the handle's stream. */
+ * fields of every non-solid cell on the device (eps in (0,1], K^-1 >= 0,
+ * rho0 > 0, all finite) and returns LBM_EINVAL if a value is out of range,
+ * or if m->solid is set on a handle created without solid_mask.  Resets the
+ * step count.  Synchronises the handle's stream. */
 lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m);
 
 /* Advance nsteps >= 0 time steps, asynchronously on the handle's stream. */

@@ -41,13 +41,15 @@ class lbm_desc(C.Structure):
         ("A", C.c_double), ("beta", C.c_double),
         ("face", lbm_face * 6),
         ("diag_every", C.c_int),
+        ("solid_mask", C.c_int),
+        ("solid_contact_angle_deg", C.c_double),
     ]
 
 
 class lbm_medium(C.Structure):
     _fields_ = [("eps", C.c_void_p), ("kinv", C.c_void_p), ("rho0", C.c_void_p),
                 ("vel0", C.c_void_p), ("c0", C.c_void_p), ("eps_uniform", C.c_double),
-                ("kinv_uniform", C.c_double * 3)]
+                ("kinv_uniform", C.c_double * 3), ("solid", C.c_void_p)]
 
 
 class LbmError(RuntimeError):

@@ -60,21 +60,24 @@ struct LatDev {
     int physics;
     int forch, eps_grad;
     int uniform_eps, uniform_kinv;
-    int wall_lo[3], wall_hi[3], res_lo[3], res_hi[3];
+    uint32_t wall_faces, res_faces;   // bit f: face f (-x,+x,-y,+y,-z,+z) is a wall / a reservoir
     double eps_u, kinv_u[3];
     double G[3];
     double k1, k0;              // viscosity law, per-cell factor e^{k1 C + k0}
     double nu1, nu2;            // two-fluid viscosities
     double tau_d, D;            // solute relaxation time and diffusivity
     double A, beta;             // surface tension, recolouring
-    double face_rho[6], face_conc[6], face_cw[6];
+    double face_rho[6], face_conc[6];
+    double face_cw[7];          // wall colour (1 + cos theta)/2 of each face; [6]: obstacles
     void *f[2];                 // hydrodynamic populations (deviations f - w), copies A, B
     void *h[2];                 // second lattice (solute h or fluid-1 g), copies A, B
     void *fm[2], *hm[2];        // split 16-bit codecs: per-cell FP32 mass planes of each copy
     void *eps, *kinv, *mom, *rho1;
+    const void *links;          // obstacle mask as link words (bit 0: solid, bit q: x - v_q solid), or null
     double *partials, *diag;
     int *err;
     uint32_t div_nx[3], div_nxy[3];   // magic numbers of the divisions by nx and nx*ny
+    uint32_t pstride;           // elements from one population plane to the next (>= ncell)
 };
 
 // Arguments of one batched launch: lattice l owns logical blocks
@@ -124,34 +127,50 @@ __device__ inline int find_lattice(const BatchArgs &a, int gb)
     return l;
 }
 
-__device__ inline int cell_type(const LatDev *L, int x, int y, int z, int &face)
+// link word of a cell: 0 without an obstacle mask
+__device__ inline uint32_t link_word(const LatDev *L, uint32_t idx)
 {
-    const int c[3] = {x, y, z};
-    const int n[3] = {L->nx, L->ny, L->nz};
-    for (int a = 0; a < 3; ++a) {
-        if (L->wall_lo[a] && c[a] == 0) { face = 2 * a; return CELL_SOLID; }
-        if (L->wall_hi[a] && c[a] == n[a] - 1) { face = 2 * a + 1; return CELL_SOLID; }
-    }
-    for (int a = 0; a < 3; ++a) {
-        if (L->res_lo[a] && c[a] == 0) { face = 2 * a; return CELL_RES; }
-        if (L->res_hi[a] && c[a] == n[a] - 1) { face = 2 * a + 1; return CELL_RES; }
-    }
-    face = -1;
-    return CELL_FLUID;
+    return L->links ? static_cast<const GL uint32_t *>((const GL void *)L->links)[idx] : 0u;
+}
+
+// Class of a cell: a wall-face cell is solid (face = its face); else an
+// obstacle of the mask is solid (face = 6); else a reservoir-face cell
+// belongs to that reservoir; else fluid.
+// Faces of the box a cell lies on, as bits f = 2 axis + (0: low, 1: high).
+__device__ inline uint32_t faces_of(const LatDev *L, int x, int y, int z)
+{
+    return uint32_t(x == 0) | uint32_t(x == L->nx - 1) << 1 | uint32_t(y == 0) << 2 |
+           uint32_t(y == L->ny - 1) << 3 | uint32_t(z == 0) << 4 | uint32_t(z == L->nz - 1) << 5;
+}
+
+// Class of a cell: a wall-face cell is solid (face = its face); else an
+// obstacle of the mask is solid (face = 6); else a reservoir-face cell
+// belongs to that reservoir; else fluid.  The lowest face wins where faces
+// meet.  Branch-free: selects on the face bits.
+__device__ inline int cell_type(const LatDev *L, int x, int y, int z, uint32_t lw, int &face)
+{
+    const uint32_t on = faces_of(L, x, y, z);
+    const uint32_t wall = on & L->wall_faces, res = on & L->res_faces;
+    const bool obst = (lw & 1u) != 0;
+    face = wall ? int(__builtin_ctz(wall)) : (obst ? 6 : (res ? int(__builtin_ctz(res)) : -1));
+    return (wall || obst) ? CELL_SOLID : (res ? CELL_RES : CELL_FLUID);
 }
 
 // Neighbourhood of a fluid cell: wrapped coordinates of x-1 / x+1 etc. as
-// flat offsets, and whether the cell beyond each face of the cell is solid.
+// flat offsets, and the set of links whose upstream cell x - v_q is solid.
 // A fluid cell is never on a wall or reservoir plane, so on non-periodic axes
 // x-1 and x+1 are always inside the box.
 struct Nbr {
     uint32_t xm, x0, xp;        // x offsets
     uint32_t ym, y0, yp;        // y * nx
     uint32_t zm, z0, zp;        // z * nx * ny
-    bool sxm, sxp, sym, syp, szm, szp;
+    uint32_t bb;                // bit q (1..18): x - v_q is solid (bounce-back link)
 };
 
-__device__ inline Nbr neighbours(const LatDev *L, int x, int y, int z)
+// lw: the cell's link word (obstacle mask); without a mask the bounce-back
+// links follow from the wall faces: a wall plane at x - 1 cuts every link
+// with c_x > 0, and so on.
+__device__ inline Nbr neighbours(const LatDev *L, int x, int y, int z, uint32_t lw)
 {
     Nbr b;
     const uint32_t nx = L->nx, ny = L->ny, nz = L->nz, nxy = nx * ny;
@@ -164,12 +183,17 @@ __device__ inline Nbr neighbours(const LatDev *L, int x, int y, int z)
     b.z0 = z * nxy;
     b.zm = (z ? z - 1 : nz - 1) * nxy;
     b.zp = ((uint32_t)z + 1 < nz ? z + 1 : 0) * nxy;
-    b.sxm = L->wall_lo[0] && x == 1;
-    b.sxp = L->wall_hi[0] && (uint32_t)x + 2 == nx;
-    b.sym = L->wall_lo[1] && y == 1;
-    b.syp = L->wall_hi[1] && (uint32_t)y + 2 == ny;
-    b.szm = L->wall_lo[2] && z == 1;
-    b.szp = L->wall_hi[2] && (uint32_t)z + 2 == nz;
+    if (L->links) {
+        b.bb = lw & ~1u;
+    } else {
+        // wall planes one cell away from this cell, as face bits
+        const uint32_t w = L->wall_faces &
+                           (uint32_t(x == 1) | uint32_t((uint32_t)x + 2 == nx) << 1 | uint32_t(y == 1) << 2 |
+                            uint32_t((uint32_t)y + 2 == ny) << 3 | uint32_t(z == 1) << 4 |
+                            uint32_t((uint32_t)z + 2 == nz) << 5);
+        b.bb = (w & 1u ? XP : 0u) | (w & 2u ? XN : 0u) | (w & 4u ? YP : 0u) | (w & 8u ? YN : 0u) |
+               (w & 16u ? ZP : 0u) | (w & 32u ? ZN : 0u);
+    }
     return b;
 }
 
@@ -184,19 +208,18 @@ __device__ inline uint32_t shifted(const Nbr &b)
     return ox + oy + oz;
 }
 
-// is the cell x + s*v_q solid?
+// is the cell x + s*v_q solid?  (x + v_q = x - v_opp(q))
 template <int Q, int SIGN>
 __device__ inline bool shifted_solid(const Nbr &b)
 {
-    constexpr int sx = SIGN * cx(Q), sy = SIGN * cy(Q), sz = SIGN * cz(Q);
-    bool s = false;
-    if (sx < 0) s = s || b.sxm;
-    if (sx > 0) s = s || b.sxp;
-    if (sy < 0) s = s || b.sym;
-    if (sy > 0) s = s || b.syp;
-    if (sz < 0) s = s || b.szm;
-    if (sz > 0) s = s || b.szp;
-    return s;
+    constexpr int bitq = SIGN < 0 ? Q : opp(Q);
+    return ((b.bb >> bitq) & 1u) != 0;
+}
+
+// does any cell of the wave have a solid upstream neighbour?  (wave-uniform)
+__device__ inline bool wave_near_solid(const Nbr &b)
+{
+    return __builtin_amdgcn_ballot_w64(b.bb != 0u) != 0;
 }
 
 template <class T>
@@ -224,8 +247,6 @@ __device__ inline GL T *at(GL T *p, uint32_t i)
     return reinterpret_cast<GL T *>(reinterpret_cast<GL char *>(p) + i * uint32_t(sizeof(T)));
 }
 
-// Pull streaming (Eqs. lbe2, boltzeqD): f_q(x) = f~_q(x - v_q), or
-// f~_opp(q)(x) when x - v_q is solid (halfway bounce-back).
 template <class R>
 __device__ inline R ldg(const void *base, uint32_t i)
 {
@@ -238,31 +259,57 @@ __device__ inline void stg(void *base, uint32_t i, R v)
     *at(static_cast<GL R *>((GL void *)base), i) = v;
 }
 
-// Split codecs: a population is w_q m + r_q, with the per-cell mass m in an
-// FP32 plane M and the remainder r_q in the 16-bit planes.
-template <class S, int Q>
-__device__ inline typename Codec<S>::R decode(const void *P, const void *M, uint32_t n, int pq, uint32_t src)
+// element i of plane k of a field with n values per plane (64-bit uniform
+// plane base, 32-bit offset within the plane)
+template <class R>
+__device__ inline R ldp(const void *base, uint32_t n, int k, uint32_t i)
 {
-    using R = typename Codec<S>::R;
-    const R r = Codec<S>::load(at(plane<S>(P, n, pq), src));
-    if constexpr (Codec<S>::split) return fma(weight<R>(Q), ldg<R>(M, src), r);
-    else return r;
+    return *at(plane<R>(base, n, k), i);
 }
 
+template <class R>
+__device__ inline void stp(void *base, uint32_t n, int k, uint32_t i, R v)
+{
+    *at(plane_w<R>(base, n, k), i) = v;
+}
+
+// Pull streaming (Eqs. lbe2, boltzeqD): f_q(x) = f~_q(x - v_q), or
+// f~_opp(q)(x) when x - v_q is solid (halfway bounce-back).
+//
+// Source of direction Q in one uniform plane base: the plane pair
+// {Q, opp(Q)} is addressed from the lower plane, so the streamed value
+// (plane Q at x - v_q) and the bounced one (plane opp(Q) at x itself) are both
+// 32-bit offsets from the same base and a bounce-back is one select (n is the
+// plane stride; the library keeps 2 n * sizeof(storage) <= 2^32 bytes).
+template <int Q>
+__device__ inline uint32_t pair_offset(const Nbr &b, uint32_t n, uint32_t idx, bool bb)
+{
+    const uint32_t src = shifted<Q, -1>(b);
+    if constexpr (Q < opp(Q)) return bb ? n + idx : src;
+    else return bb ? idx : n + src;
+}
+
+template <int Q>
+constexpr int pair_lo() { return Q < opp(Q) ? Q : opp(Q); }
+
+// Split codecs: a population is w_q m + r_q, with the per-cell mass m in an
+// FP32 plane M and the remainder r_q in the 16-bit planes; a bounced link
+// takes both from the cell itself.  BB = false: no cell of the wave has a
+// solid upstream neighbour.
 template <class S, bool BB, int Q = 0>
 __device__ inline void split_loads(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
                                    typename Codec<S>::R *r, typename Codec<S>::R *m)
 {
     using R = typename Codec<S>::R;
-    uint32_t src = shifted<Q, -1>(b);
-    int pq = Q;
     if constexpr (BB && Q != 0) {
         const bool s = shifted_solid<Q, -1>(b);
-        pq = s ? opp(Q) : Q;
-        src = s ? idx : src;
+        r[Q] = Codec<S>::load(at(plane<S>(P, n, pair_lo<Q>()), pair_offset<Q>(b, n, idx, s)));
+        m[Q] = ldg<R>(M, s ? idx : shifted<Q, -1>(b));
+    } else {
+        const uint32_t src = shifted<Q, -1>(b);
+        r[Q] = Codec<S>::load(at(plane<S>(P, n, Q), src));
+        m[Q] = ldg<R>(M, src);
     }
-    r[Q] = Codec<S>::load(at(plane<S>(P, n, pq), src));
-    m[Q] = ldg<R>(M, src);
     if constexpr (Q + 1 < NQ) split_loads<S, BB, Q + 1>(P, M, n, idx, b, r, m);
 }
 
@@ -280,22 +327,21 @@ __device__ inline void pull_each(const void *P, const void *M, uint32_t n, uint3
     } else {
         if constexpr (BB && Q != 0) {
             const bool s = shifted_solid<Q, -1>(b);
-            out[Q] = decode<S, Q>(P, M, n, s ? opp(Q) : Q, s ? idx : shifted<Q, -1>(b));
+            out[Q] = Codec<S>::load(at(plane<S>(P, n, pair_lo<Q>()), pair_offset<Q>(b, n, idx, s)));
         } else {
-            out[Q] = decode<S, Q>(P, M, n, Q, shifted<Q, -1>(b));
+            out[Q] = Codec<S>::load(at(plane<S>(P, n, Q), shifted<Q, -1>(b)));
         }
         if constexpr (Q + 1 < NQ) pull_each<S, BB, Q + 1>(P, M, n, idx, b, out);
     }
 }
 
-// Waves without a wall-adjacent cell (all but a thin layer) take the path
-// without bounce-back selects: uniform plane bases + 32-bit offsets only.
+// Pull of one lattice.  Waves without a solid upstream neighbour (all but a
+// thin layer next to walls and obstacles) take the path without selects.
 template <class S>
 __device__ inline void pull_all(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
                                 typename Codec<S>::R *out)
 {
-    const bool near_wall = b.sxm || b.sxp || b.sym || b.syp || b.szm || b.szp;
-    if (__builtin_amdgcn_ballot_w64(near_wall) != 0) pull_each<S, true>(P, M, n, idx, b, out);
+    if (wave_near_solid(b)) pull_each<S, true>(P, M, n, idx, b, out);
     else pull_each<S, false>(P, M, n, idx, b, out);
 }
 
@@ -348,16 +394,26 @@ __device__ inline uint32_t udiv(uint32_t n, const uint32_t g[3])
 }
 
 // grad(eps) (times eps) by sum_q w_q eps(x + v_q) v_q; a solid neighbour
-// takes eps(x).  The caller scales by 3 / eps(x).
-template <class R, int Q = 1>
-__device__ inline void eps_grad_acc(const void *E, const Nbr &b, R e0, R &gx, R &gy, R &gz)
+// takes eps(x).  The caller scales by 3 / eps(x).  BB = false: no cell of the
+// wave has a solid neighbour.
+template <class R, bool BB, int Q = 1>
+__device__ inline void eps_grad_each(const void *E, const Nbr &b, R e0, R &gx, R &gy, R &gz)
 {
-    const R e = shifted_solid<Q, 1>(b) ? e0 : ldg<R>(E, shifted<Q, 1>(b));
+    R e;
+    if constexpr (BB) e = shifted_solid<Q, 1>(b) ? e0 : ldg<R>(E, shifted<Q, 1>(b));
+    else e = ldg<R>(E, shifted<Q, 1>(b));
     const R we = weight<R>(Q) * e;
     if (cx(Q)) gx += cx(Q) > 0 ? we : -we;
     if (cy(Q)) gy += cy(Q) > 0 ? we : -we;
     if (cz(Q)) gz += cz(Q) > 0 ? we : -we;
-    if constexpr (Q + 1 < NQ) eps_grad_acc<R, Q + 1>(E, b, e0, gx, gy, gz);
+    if constexpr (Q + 1 < NQ) eps_grad_each<R, BB, Q + 1>(E, b, e0, gx, gy, gz);
+}
+
+template <class R>
+__device__ inline void eps_grad_acc(const void *E, const Nbr &b, R e0, R &gx, R &gy, R &gz)
+{
+    if (wave_near_solid(b)) eps_grad_each<R, true>(E, b, e0, gx, gy, gz);
+    else eps_grad_each<R, false>(E, b, e0, gx, gy, gz);
 }
 
 // colour gradient, Eq. macros: F = sum_{q != 0} rho_1(x + v_q) v_q
@@ -642,19 +698,21 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
     R m_rho = 0, m_C = 0, m_s4 = 0, m_u[3] = {0, 0, 0}, m_up[3] = {0, 0, 0};
     int type = CELL_SOLID;
     int x = 0, y = 0, z = 0, face = -1;
+    uint32_t lw = 0;
     if (idx < ncell) {
         z = udiv(idx, L->div_nxy);
         const uint32_t r = idx - uint32_t(z) * nxy;
         y = udiv(r, L->div_nx);
         x = r - uint32_t(y) * nx;
-        type = cell_type(L, x, y, z, face);
+        lw = link_word(L, idx);
+        type = cell_type(L, x, y, z, lw, face);
     }
     if (type == CELL_FLUID) {
-        const Nbr b = neighbours(L, x, y, z);
+        const Nbr b = neighbours(L, x, y, z, lw);
         R d[NQ];
-        pull_all<S>(L->f[src], L->fm[src], ncell, idx, b, d);
+        pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
         R hq[NQ];
-        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], L->hm[src], ncell, idx, b, hq);
+        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], L->hm[src], L->pstride, idx, b, hq);
 
         R drho = 0, jx = 0, jy = 0, jz = 0;
         moments_acc<R>(d, drho, jx, jy, jz);
@@ -670,8 +728,8 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
             kinv[2] = R(L->kinv_u[2]);
         } else {
             kinv[0] = ldg<R>(L->kinv, idx);
-            kinv[1] = ldg<R>(L->kinv, ncell + idx);
-            kinv[2] = ldg<R>(L->kinv, 2 * ncell + idx);
+            kinv[1] = ldp<R>(L->kinv, ncell, 1, idx);
+            kinv[2] = ldp<R>(L->kinv, ncell, 2, idx);
         }
         const R ie = rcp(eps);
 
@@ -724,25 +782,25 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
             const R omd = R(1) / R(L->tau_d);
             const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
             collide_h<R>(hq, R(1) - omd, H, vs);
-            store_all<S>(L->h[dst], L->hm[dst], ncell, idx, hq);
+            store_all<S>(L->h[dst], L->hm[dst], L->pstride, idx, hq);
         } else if constexpr (PHYS == PH_IMMISCIBLE) {
             R g[NQ];
             const R rec = Fn > R(0) ? R(L->beta) * C * (R(1) - C) * rho * iFn : R(0);
             const R Cw[3] = {C * weight<R>(0), C * weight<R>(1), C * weight<R>(7)};
             const R rw[3] = {R(0), rec * weight<R>(1), rec * weight<R>(7) * R(0.70710678118654752440)};
             recolour<R>(g, d, C, Cw, rw, F);
-            store_all<S>(L->h[dst], L->hm[dst], ncell, idx, g);
+            store_all<S>(L->h[dst], L->hm[dst], L->pstride, idx, g);
         }
-        store_all<S>(L->f[dst], L->fm[dst], ncell, idx, d);
+        store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
 
         if (mom) {
             void *M = L->mom;
-            const R up[3] = {ldg<R>(M, ncell + idx), ldg<R>(M, 2 * ncell + idx), ldg<R>(M, 3 * ncell + idx)};
+            const R up[3] = {ldp<R>(M, ncell, 1, idx), ldp<R>(M, ncell, 2, idx), ldp<R>(M, ncell, 3, idx)};
             stg<R>(M, idx, rho);
-            stg<R>(M, ncell + idx, u[0]);
-            stg<R>(M, 2 * ncell + idx, u[1]);
-            stg<R>(M, 3 * ncell + idx, u[2]);
-            stg<R>(M, 4 * ncell + idx, C);
+            stp<R>(M, ncell, 1, idx, u[0]);
+            stp<R>(M, ncell, 2, idx, u[1]);
+            stp<R>(M, ncell, 3, idx, u[2]);
+            stp<R>(M, ncell, 4, idx, C);
             has = true;
             m_rho = rho;
             m_C = C;
@@ -782,16 +840,17 @@ __global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
     const int y = udiv(r, L->div_nx);
     const int x = r - uint32_t(y) * nx;
     int face;
-    const int type = cell_type(L, x, y, z, face);
+    const uint32_t lw = link_word(L, idx);
+    const int type = cell_type(L, x, y, z, lw, face);
     R v;
     if (type == CELL_SOLID) {
         v = R(L->face_cw[face]);
     } else if (type == CELL_RES) {
         v = R(L->face_conc[face]) * R(L->face_rho[face]);
     } else {
-        const Nbr b = neighbours(L, x, y, z);
+        const Nbr b = neighbours(L, x, y, z, lw);
         R g[NQ];
-        pull_all<S>(L->h[src], L->hm[src], ncell, idx, b, g);
+        pull_all<S>(L->h[src], L->hm[src], L->pstride, idx, b, g);
         v = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v += g[q];
@@ -836,6 +895,43 @@ struct InitArgs {
 template <class R>
 __device__ inline bool bad(R v) { return !isfinite(v); }
 
+// Link words of the obstacle mask: bit 0 = the cell is solid (wall face or
+// mask), bit q = the cell x - v_q is solid (periodic axes wrap).  Cells on
+// the face plane of a non-periodic axis are never fluid and get bit 0 only.
+// solid may be null (no obstacles: the words then encode the walls alone).
+__global__ __launch_bounds__(BLOCK) void k_links(const LatDev *L, const unsigned char *solid, uint32_t *links)
+{
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= uint32_t(L->ncell)) return;
+    const int n[3] = {L->nx, L->ny, L->nz};
+    const uint32_t nxy = uint32_t(n[0]) * uint32_t(n[1]);
+    const int z = idx / nxy;
+    const uint32_t r = idx - uint32_t(z) * nxy;
+    const int y = r / n[0], x = r - uint32_t(y) * n[0];
+    const int c[3] = {x, y, z};
+    const uint32_t on = faces_of(L, x, y, z);
+    const bool edge = (on & (L->wall_faces | L->res_faces)) != 0;
+    const bool wall = (on & L->wall_faces) != 0;
+    uint32_t w = (wall || (solid && solid[idx])) ? 1u : 0u;
+    if (!edge) {
+        for (int q = 1; q < NQ; ++q) {
+            const int d[3] = {cx(q), cy(q), cz(q)};
+            int u[3];
+            bool s = false;
+            for (int a = 0; a < 3; ++a) {
+                u[a] = c[a] - d[a];
+                if (u[a] < 0) u[a] += n[a];
+                if (u[a] >= n[a]) u[a] -= n[a];
+                if (((L->wall_faces >> (2 * a)) & 1u) && u[a] == 0) s = true;
+                if (((L->wall_faces >> (2 * a + 1)) & 1u) && u[a] == n[a] - 1) s = true;
+            }
+            const uint32_t j = uint32_t(u[0]) + uint32_t(n[0]) * (uint32_t(u[1]) + uint32_t(n[1]) * uint32_t(u[2]));
+            if (s || (solid && solid[j])) w |= 1u << q;
+        }
+    }
+    links[idx] = w;
+}
+
 // colour field of the initial state (two-fluid): C0 rho0 in fluid cells.
 template <class R>
 __global__ __launch_bounds__(BLOCK) void k_init_colour(const InitArgs<R> ia)
@@ -848,7 +944,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_colour(const InitArgs<R> ia)
     const uint32_t r = idx - uint32_t(z) * nxy;
     const int y = r / nx, x = r - uint32_t(y) * nx;
     int face;
-    const int type = cell_type(L, x, y, z, face);
+    const int type = cell_type(L, x, y, z, link_word(L, idx), face);
     R v;
     if (type == CELL_SOLID) v = R(L->face_cw[face]);
     else if (type == CELL_RES) v = R(L->face_conc[face]) * R(L->face_rho[face]);
@@ -872,18 +968,21 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
     const uint32_t r = idx - uint32_t(z) * nxy;
     const int y = r / nx, x = r - uint32_t(y) * nx;
     int face;
-    const int type = cell_type(L, x, y, z, face);
+    const uint32_t lw = link_word(L, idx);
+    const int type = cell_type(L, x, y, z, lw, face);
 
     const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
     R kinv[3];
-    for (int a = 0; a < 3; ++a) kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : ldg<R>(L->kinv, a * ncell + idx);
+    for (int a = 0; a < 3; ++a) kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : ldp<R>(L->kinv, ncell, a, idx);
     const R rho0 = ia.rho0 ? ia.rho0[idx] : R(1);
     R u0[3];
     for (int a = 0; a < 3; ++a) u0[a] = ia.vel0 ? ia.vel0[a * n + idx] : R(0);
     const R c0 = ia.c0 ? ia.c0[idx] : R(0);
-    if (!(eps > R(0) && eps <= R(1)) || bad(kinv[0]) || bad(kinv[1]) || bad(kinv[2]) ||
-        kinv[0] < R(0) || kinv[1] < R(0) || kinv[2] < R(0) || !(rho0 > R(0)) || bad(rho0) ||
-        bad(u0[0]) || bad(u0[1]) || bad(u0[2]) || bad(c0)) {
+    // solid cells carry no state: their fields are not used
+    if (type != CELL_SOLID &&
+        (!(eps > R(0) && eps <= R(1)) || bad(kinv[0]) || bad(kinv[1]) || bad(kinv[2]) ||
+         kinv[0] < R(0) || kinv[1] < R(0) || kinv[2] < R(0) || !(rho0 > R(0)) || bad(rho0) ||
+         bad(u0[0]) || bad(u0[1]) || bad(u0[2]) || bad(c0))) {
         *L->err = 1;
     }
 
@@ -902,7 +1001,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
         mrho = rb;
         mC = PHYS == PH_SINGLE ? R(0) : cb;
     } else {
-        const Nbr b = neighbours(L, x, y, z);
+        const Nbr b = neighbours(L, x, y, z, lw);
         const R C = PHYS == PH_SINGLE ? R(0) : c0;
         R nu;
         if constexpr (PHYS == PH_IMMISCIBLE) nu = C * R(L->nu1) + (R(1) - C) * R(L->nu2);
@@ -949,15 +1048,15 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
         mC = C;
     }
     for (int cpy = 0; cpy < 2; ++cpy) {
-        store_all<S>(L->f[cpy], L->fm[cpy], ncell, idx, d);
-        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], L->hm[cpy], ncell, idx, hq);
+        store_all<S>(L->f[cpy], L->fm[cpy], L->pstride, idx, d);
+        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], L->hm[cpy], L->pstride, idx, hq);
     }
     void *M = L->mom;
     stg<R>(M, idx, mrho);
-    stg<R>(M, ncell + idx, mu[0]);
-    stg<R>(M, 2 * ncell + idx, mu[1]);
-    stg<R>(M, 3 * ncell + idx, mu[2]);
-    stg<R>(M, 4 * ncell + idx, mC);
+    stp<R>(M, ncell, 1, idx, mu[0]);
+    stp<R>(M, ncell, 2, idx, mu[1]);
+    stp<R>(M, ncell, 3, idx, mu[2]);
+    stp<R>(M, ncell, 4, idx, mC);
 }
 
 // diagnostics of the moments buffer (used after set-up: residual 0)
@@ -973,10 +1072,10 @@ __global__ __launch_bounds__(BLOCK) void k_diag_moments(const LatDev *L)
         const uint32_t r = idx - uint32_t(z) * nxy;
         const int y = r / nx, x = r - uint32_t(y) * nx;
         int face;
-        if (cell_type(L, x, y, z, face) == CELL_FLUID) {
+        if (cell_type(L, x, y, z, link_word(L, idx), face) == CELL_FLUID) {
             const void *M = L->mom;
-            const R u[3] = {ldg<R>(M, ncell + idx), ldg<R>(M, 2 * ncell + idx), ldg<R>(M, 3 * ncell + idx)};
-            const R rho = ldg<R>(M, idx), C = ldg<R>(M, 4 * ncell + idx);
+            const R u[3] = {ldp<R>(M, ncell, 1, idx), ldp<R>(M, ncell, 2, idx), ldp<R>(M, ncell, 3, idx)};
+            const R rho = ldg<R>(M, idx), C = ldp<R>(M, ncell, 4, idx);
             R s4 = 0;
             if (L->physics == PH_MISCIBLE)
                 s4 = (L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx)) * C;
@@ -1000,7 +1099,7 @@ __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, in
     const void *M = which == 0 ? L->fm[src] : L->hm[src];
     const R m = Codec<S>::split ? ldg<R>(M, idx) : R(0);
     for (int q = 0; q < NQ; ++q)
-        dst[size_t(q) * ncell + idx] = fma(weight<R>(q), m, Codec<S>::load(at(plane<S>(P, ncell, q), idx)));
+        dst[size_t(q) * ncell + idx] = fma(weight<R>(q), m, Codec<S>::load(at(plane<S>(P, L->pstride, q), idx)));
 }
 
 }  // namespace plbm

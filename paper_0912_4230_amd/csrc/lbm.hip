@@ -31,8 +31,18 @@ size_t storage_bytes(int storage)
 
 size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
+// Elements from one population plane to the next.  16-bit planes are padded
+// by 128 bytes each: the 38 read and 38 write streams of a step then do not
+// all sit at the same offset modulo the (power-of-two) plane size, which
+// measured 4-7% faster on 16-bit storage and no better on 4- and 8-byte.
+size_t plane_stride(const lbm_desc *d)
+{
+    const size_t n = (size_t)d->nx * d->ny * d->nz;
+    return storage_bytes(d->storage) == 2 ? n + 128 / 2 : n;
+}
+
 struct Layout {
-    size_t lat, err, diag, partials, eps, kinv, mom, rho1, f0, f1, h0, h1, fm0, fm1, hm0, hm1, total;
+    size_t lat, err, diag, partials, eps, kinv, mom, rho1, links, f0, f1, h0, h1, fm0, fm1, hm0, hm1, total;
 };
 
 bool split_storage(int storage) { return storage == LBM_BF16_SPLIT || storage == LBM_F16_SPLIT; }
@@ -46,6 +56,10 @@ bool valid_desc(const lbm_desc *d)
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
     const long long ncell = (long long)d->nx * d->ny * d->nz;
     if (ncell > (1LL << 31) - BLOCK) return false;
+    // planes are addressed by 32-bit byte offsets from a uniform base: a
+    // field plane, or a pair of population planes for the bounce-back selects
+    const unsigned long long pair = 2ULL * plane_stride(d) * storage_bytes(d->storage);
+    if ((unsigned long long)ncell * real_bytes(d->storage) > (1ULL << 32) || pair > (1ULL << 32)) return false;
     if (d->physics < LBM_SINGLE || d->physics > LBM_IMMISCIBLE) return false;
     if (d->storage < LBM_F64 || d->storage > LBM_F16_SPLIT) return false;
     const int n[3] = {d->nx, d->ny, d->nz};
@@ -76,6 +90,8 @@ bool valid_desc(const lbm_desc *d)
     }
     if (d->physics == LBM_MISCIBLE && (!(d->tau_d > 0.5) || !is_fin(d->tau_d))) return false;
     if (d->diag_every < 0) return false;
+    if (d->solid_mask != 0 && d->solid_mask != 1) return false;
+    if (d->solid_mask && d->physics == LBM_IMMISCIBLE && !is_fin(d->solid_contact_angle_deg)) return false;
     return true;
 }
 
@@ -94,10 +110,12 @@ Layout layout(const lbm_desc *d)
     L.kinv = o;      o = align_up(o + 3 * n * rb);
     L.mom = o;       o = align_up(o + 5 * n * rb);
     L.rho1 = o;      if (d->physics == LBM_IMMISCIBLE) o = align_up(o + n * rb);
-    L.f0 = o;        o = align_up(o + NQ * n * sb);
-    L.f1 = o;        o = align_up(o + NQ * n * sb);
-    L.h0 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * n * sb);
-    L.h1 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * n * sb);
+    L.links = o;     if (d->solid_mask) o = align_up(o + n * sizeof(uint32_t));
+    const size_t ps = plane_stride(d);
+    L.f0 = o;        o = align_up(o + NQ * ps * sb);
+    L.f1 = o;        o = align_up(o + NQ * ps * sb);
+    L.h0 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * ps * sb);
+    L.h1 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * ps * sb);
     const bool sp = split_storage(d->storage), two = d->physics != LBM_SINGLE;
     L.fm0 = o;       if (sp) o = align_up(o + n * sizeof(float));
     L.fm1 = o;       if (sp) o = align_up(o + n * sizeof(float));
@@ -150,10 +168,16 @@ lbm_status dev_err(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE
 
 using Launch = void (*)(const BatchArgs &, int blocks, hipStream_t);
 
+// Dynamic LDS reserved by every step launch (unused by the kernel): it caps
+// residency at 4 blocks of 256 threads per CU, i.e. 4 waves per SIMD.  Step
+// kernels that fit in fewer than 103 VGPRs would otherwise run 5 waves per
+// SIMD, which measured 2-3% slower on the FP32 miscible and two-fluid steps.
+constexpr size_t STEP_LDS_RESERVE = 33 * 1024;
+
 template <int P, class S>
 void launch_step(const BatchArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<P, S>), dim3(blocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_step<P, S>), dim3(blocks), dim3(BLOCK), STEP_LDS_RESERVE, s, a);
 }
 
 template <class S>
@@ -315,16 +339,17 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
         const size_t bpp = plane_cells / BLOCK;
         D.bpp = (PLBM_SLAB && plane_cells % BLOCK == 0 && bpp % 8 == 0) ? int(bpp) : 0;
     }
+    D.pstride = uint32_t(plane_stride(d));
     magic_divisor(uint32_t(d->nx), D.div_nx);
     magic_divisor(uint32_t(d->nx) * uint32_t(d->ny), D.div_nxy);
     D.physics = d->physics;
     D.forch = d->forchheimer ? 1 : 0;
     D.eps_grad = d->eps_gradient ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
-        D.wall_lo[a] = d->face[2 * a].kind == LBM_FACE_WALL;
-        D.wall_hi[a] = d->face[2 * a + 1].kind == LBM_FACE_WALL;
-        D.res_lo[a] = d->face[2 * a].kind == LBM_FACE_RESERVOIR;
-        D.res_hi[a] = d->face[2 * a + 1].kind == LBM_FACE_RESERVOIR;
+        for (int f = 2 * a; f < 2 * a + 2; ++f) {
+            if (d->face[f].kind == LBM_FACE_WALL) D.wall_faces |= 1u << f;
+            if (d->face[f].kind == LBM_FACE_RESERVOIR) D.res_faces |= 1u << f;
+        }
         D.G[a] = d->G[a];
     }
     D.k1 = d->k1;
@@ -341,6 +366,7 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
         D.face_conc[f] = d->face[f].conc;
         D.face_cw[f] = 0.5 * (1.0 + cos(d->face[f].contact_angle_deg * pi / 180.0));
     }
+    D.face_cw[6] = d->solid_mask ? 0.5 * (1.0 + cos(d->solid_contact_angle_deg * pi / 180.0)) : 0.5;
     char *w = h->ws;
     D.f[0] = w + L.f0;
     D.f[1] = w + L.f1;
@@ -355,6 +381,7 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     D.kinv = w + L.kinv;
     D.mom = w + L.mom;
     D.rho1 = d->physics == LBM_IMMISCIBLE ? w + L.rho1 : nullptr;
+    D.links = d->solid_mask ? w + L.links : nullptr;
     D.partials = reinterpret_cast<double *>(w + L.partials);
     D.diag = reinterpret_cast<double *>(w + L.diag);
     D.err = reinterpret_cast<int *>(w + L.err);
@@ -378,12 +405,17 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     if (!m->kinv)
         for (int a = 0; a < 3; ++a)
             if (!(m->kinv_uniform[a] >= 0.0) || !is_fin(m->kinv_uniform[a])) return LBM_EINVAL;
+    if (m->solid && !h->d.solid_mask) return LBM_EINVAL;
     lbm_status st;
     if ((st = dev_err(hipMemcpyAsync(h->dev, &D, sizeof(LatDev), hipMemcpyHostToDevice, h->stream)))) return st;
     static const int zero = 0;
     if ((st = dev_err(hipMemcpyAsync(D.err, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream)))) return st;
     if (m->eps && (st = dev_err(hipMemcpyAsync(D.eps, m->eps, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
     if (m->kinv && (st = dev_err(hipMemcpyAsync(D.kinv, m->kinv, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    if (D.links) {
+        uint32_t *links = static_cast<uint32_t *>(const_cast<void *>(D.links));
+        hipLaunchKernelGGL(k_links, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev, m->solid, links);
+    }
     switch (h->d.physics) {
     case LBM_SINGLE: init_for_storage<PH_SINGLE>(h, m, h->nblocks); break;
     case LBM_MISCIBLE: init_for_storage<PH_MISCIBLE>(h, m, h->nblocks); break;

@@ -33,6 +33,8 @@ def make_desc(p: I.Problem, storage: int = B.LBM_F32, diag_every: int = 0) -> B.
         d.face[f].conc = float(F.conc)
         d.face[f].contact_angle_deg = float(F.angle)
     d.diag_every = int(diag_every)
+    d.solid_mask = int(p.solid is not None)
+    d.solid_contact_angle_deg = float(p.solid_angle)
     return d
 
 
@@ -102,6 +104,10 @@ class Simulation:
             t = self._dev(arr)
             keep.append(t)
             setattr(m, name, t.data_ptr())
+        if p.solid is not None:
+            t = torch.from_numpy(np.ascontiguousarray(np.asarray(p.solid) != 0, dtype=np.uint8)).to(self.device)
+            keep.append(t)
+            m.solid = t.data_ptr()
         with torch.cuda.stream(self.stream):
             torch.cuda.current_stream(self.device).wait_stream(torch.cuda.default_stream(self.device))
             B.lbm_set_medium(self.h, m)

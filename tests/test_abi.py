@@ -28,10 +28,27 @@ def test_exports_every_declared_function():
         assert hasattr(L, n), n
 
 
-def test_struct_sizes_match_header():
-    # lbm_face: int + 3 doubles (padded); lbm_desc ends with an int
-    assert C.sizeof(B.lbm_face) == 32
-    assert C.sizeof(B.lbm_medium) == 5 * 8 + 8 + 24
+def test_struct_layout_matches_header(tmp_path):
+    """sizeof / offsetof of the ABI structs as the C compiler lays them out
+    from include/lbm.h, against the ctypes mirrors of the binding."""
+    fields = {"lbm_face": B.lbm_face, "lbm_desc": B.lbm_desc, "lbm_medium": B.lbm_medium}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void) {"]
+    for name, cls in fields.items():
+        lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in fields.items():
+        assert got[(name, "sizeof")] == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert got[(name, f[0])] == getattr(cls, f[0]).offset, (name, f[0])
 
 
 def test_lattice_table():
@@ -62,11 +79,13 @@ def test_workspace_size():
     dm = make_desc(I.miscible(shape=(8, 6, 5)), B.LBM_BF16_DEV)
     dm32 = make_desc(I.miscible(shape=(8, 6, 5)), B.LBM_F32)
     assert B.lbm_workspace_bytes(dm) < B.lbm_workspace_bytes(dm32)
+    # an obstacle mask adds one 32-bit link word per cell
+    assert B.lbm_workspace_bytes(_desc(solid_mask=1)) - ws == -(-n * 4 // 256) * 256
 
 
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("physics", 7), ("storage", 9), ("nu0", 0.0), ("nu0", -1.0),
-    ("a0", -1.0), ("cap", 0.0), ("diag_every", -2), ("A", 0.01),
+    ("a0", -1.0), ("cap", 0.0), ("diag_every", -2), ("A", 0.01), ("solid_mask", 2),
 ])
 def test_invalid_descriptions_rejected(field, value):
     d = _desc(**{field: value})

@@ -57,9 +57,11 @@ def test_batch_of_different_shapes_matches_single_steps():
     equals lbm_step on each."""
     import torch
     from paper_0912_4230_amd.sim import Simulation, step_batch
+    obst = I.miscible(shape=(21, 15, 12), seed=8)
+    obst.solid = I.sphere_obstacles(obst.shape, seed=9, solid_fraction=0.1, radius=(1.5, 2.5))
     probs = [I.miscible(shape=(20, 17, 13), seed=5), I.drop(shape=(24, 22, 20), radius=5.0),
-             I.miscible(shape=(33, 9, 11), seed=6), I.drop(shape=(16, 16, 16), radius=4.0)]
-    steps = [25, 40, 7, 33]
+             I.miscible(shape=(33, 9, 11), seed=6), I.drop(shape=(16, 16, 16), radius=4.0), obst]
+    steps = [25, 40, 7, 33, 19]
     a = [Simulation(p, storage="f32") for p in probs]
     step_batch(a, steps)
     for p, n, s in zip(probs, steps, a):
