@@ -189,6 +189,31 @@ def precision_leg(n=512, steps=2000, timed=200):
     return res
 
 
+def obstacle_leg(p, steps, warmup, storages=("f32", "bf16"), solid_fraction=0.1):
+    """The miscible workload with obstacle cells: 4^3 solid cubes placed with
+    probability 0.1 (seeded), every link into them bounced back.  Algorithmic
+    bytes: 320 (FP32) / 168 (16-bit) per fluid cell plus the 4-byte link word
+    of every cell."""
+    import copy
+    from paper_0912_4230_amd import inputs as I
+    n = p.shape[0]
+    q = copy.copy(p)
+    q.solid = I.block_obstacles(p.shape, seed=0, solid_fraction=solid_fraction)
+    ncell = n ** 3
+    nfluid = int((q.solid == 0).sum())
+    out = {"solid_fraction": round(1 - nfluid / ncell, 4), "obstacle": "4^3 cubes, seeded"}
+    for st in storages:
+        ms, dg = time_gpu(q, st, steps, warmup)
+        s = ms / steps
+        bpl = storage_bpl(st)
+        out[st] = {"ms_per_step": round(s, 5), "MLUPS_all_cells": round(ncell / s / 1e3, 1),
+                   "MLUPS_fluid_cells": round(nfluid / s / 1e3, 1),
+                   "achieved_GBs": round((nfluid * bpl + ncell * 4) / (s / 1e3) / 1e9, 1),
+                   "nonfinite": int(dg[7])}
+        log(f"bench: obstacles {st}: {out[st]}")
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -218,6 +243,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--precision", action="store_true",
                     help="also run the 512^3 precision form (FP32 / BF16 / FP16 storage, 2000 steps)")
     args = ap.parse_args()
@@ -284,6 +310,8 @@ def main():
                        "traffic_GB_per_launch": counter_traffic(f"k_step miscible {n} {st}")}
             log(f"bench: {st}: {s2:.4f} ms/step, speedup {ms_step / s2:.3f}")
         out["reduced_storage"] = red
+    if not args.no_obstacles and args.storage == "f32":
+        out["obstacles"] = obstacle_leg(p, min(args.steps, 300), args.warmup)
     if not args.no_serve:
         out["serving"] = serving_leg()
     if args.precision:

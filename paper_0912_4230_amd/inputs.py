@@ -260,6 +260,27 @@ def sphere_obstacles(shape, seed: int = 0, solid_fraction: float = 0.1, radius=(
     return mask.astype(np.uint8)
 
 
+def block_obstacles(shape, seed: int = 0, solid_fraction: float = 0.1, block: int = 4, origin=(0, 0, 0),
+                    free_x=2) -> np.ndarray:
+    """Seeded obstacle mask of solid cubes: the box is tiled by block^3
+    cubes (in global coordinates) and each cube is solid with probability
+    `solid_fraction`, from the counter-based generator on the cube's
+    coordinates (so crops agree with the full mask).  The `free_x` planes at
+    each end of x stay fluid (room for reservoir faces).  Returns uint8
+    (nz,ny,nx)."""
+    nx, ny, nz = shape
+    ox, oy, oz = origin
+    x = (np.arange(nx, dtype=np.int64) + ox) // block
+    y = (np.arange(ny, dtype=np.int64) + oy) // block
+    z = (np.arange(nz, dtype=np.int64) + oz) // block
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    mask = cell_uniform(seed, X, Y, Z, 2) < solid_fraction
+    if free_x:
+        mask[:, :, :free_x] = False
+        mask[:, :, nx - free_x:] = False
+    return mask.astype(np.uint8)
+
+
 def duct(shape=(4, 20, 20), G=1e-6, tau=0.8) -> Problem:
     """Body-force driven flow along x through a square duct made of obstacle
     cells: the y and z edge layers of the box are solid, every face is

@@ -72,3 +72,15 @@ def test_problem_shapes():
     d = I.drop(shape=(32, 32, 32), radius=5)
     assert d.c0.sum() == (np.sum((np.indices((32, 32, 32)) - 16) ** 2, axis=0) <= 25).sum()
     assert d.faces[4].kind == I.WALL and d.faces[4].angle == 120.0
+
+
+def test_block_obstacles_crop_and_fraction():
+    a = I.block_obstacles((40, 30, 20), seed=0, free_x=0)
+    b = I.block_obstacles((20, 10, 8), seed=0, origin=(8, 12, 4), free_x=0)
+    assert np.array_equal(a[4:12, 12:22, 8:28], b)
+    m = I.block_obstacles((64, 64, 64), seed=1, solid_fraction=0.25)
+    assert 0.18 < m.mean() < 0.3
+    assert not m[:, :, :2].any() and not m[:, :, -2:].any()
+    # whole 4^3 cubes
+    c = m[:, :, 4:60].reshape(16, 4, 16, 4, 14, 4)
+    assert np.all(c.min(axis=(1, 3, 5)) == c.max(axis=(1, 3, 5)))
