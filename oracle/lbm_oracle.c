@@ -113,12 +113,15 @@ typedef struct {
     int face_kind[6];   /* -x,+x,-y,+y,-z,+z : FACE_* */
     double face_rho[6], face_conc[6], face_angle[6];  /* reservoir rho, C; wall angle (deg) */
     double solid_angle; /* contact angle (deg) of the obstacle cells of a solid mask */
+    int full_tensor;    /* 1: K^-1 is a full symmetric tensor, 6 planes {xx,yy,zz,xy,xz,yz} */
 } orc_params;
 
 typedef struct {
     orc_params p;
     long n;                   /* number of cells */
-    double *eps, *kinv;       /* porosity; inverse permeability diagonal (3 planes) */
+    double *eps, *kinv;       /* porosity; inverse permeability: diagonal (3 planes) or
+                                 full symmetric tensor (6 planes {xx,yy,zz,xy,xz,yz}) */
+    double *ksqrt;            /* full tensor only: K^-1/2, 6 planes like kinv */
     unsigned char *type, *tface;
     double *f[2], *h[2];      /* [q*n + idx]; f as deviations f - w, h absolute */
     int cur;                  /* f[cur], h[cur] hold the current post-collision state */
@@ -251,6 +254,151 @@ static void porous_velocity(const orc_params *p, double eps, const double kinv[3
         Fext[a] = eps * p->G[a] - eps * nu * kinv[a] * Vp[a] - eps * Feps * sp * sqrt(kinv[a]) * Vp[a];
 }
 
+/* ------------------------------------------------------------------------ */
+/* Full permeability tensor (the rotated K of Eq. Ktensor).  A symmetric 3x3
+ * matrix is held as {xx, yy, zz, xy, xz, yz}.                              */
+static void sym_full(const double k[6], double M[3][3])
+{
+    M[0][0] = k[0]; M[1][1] = k[1]; M[2][2] = k[2];
+    M[0][1] = M[1][0] = k[3];
+    M[0][2] = M[2][0] = k[4];
+    M[1][2] = M[2][1] = k[5];
+}
+
+/* Eigen-decomposition M = Q diag(d) Q^T of a symmetric 3x3 matrix by the
+ * cyclic Jacobi method (Golub and Van Loan, Matrix Computations, Sec. 8.5):
+ * plane rotations annihilate the off-diagonal entries in turn until they
+ * vanish to rounding.  Columns of Q are the eigenvectors.                  */
+static void jacobi3(const double Min[3][3], double d[3], double Q[3][3])
+{
+    double A[3][3];
+    memcpy(A, Min, sizeof(A));
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Q[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        double diag = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off <= 1e-40 * diag || off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                /* rotation in the (p, q) plane that zeroes A[p][q] */
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < 3; ++k) {       /* A <- A J */
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - sn * akq;
+                    A[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) {       /* A <- J^T A */
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - sn * aqk;
+                    A[q][k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {       /* Q <- Q J */
+                    double qkp = Q[k][p], qkq = Q[k][q];
+                    Q[k][p] = c * qkp - sn * qkq;
+                    Q[k][q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    for (int i = 0; i < 3; ++i) d[i] = A[i][i];
+}
+
+/* K^-1/2: the symmetric positive semi-definite square root of K^-1,
+ * Q diag(sqrt(d)) Q^T (negative rounding residues of d taken as 0).       */
+static void sym_sqrt(const double k[6], double out[6])
+{
+    double M[3][3], Q[3][3], d[3];
+    sym_full(k, M);
+    jacobi3(M, d, Q);
+    double r[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a) acc += Q[i][a] * sqrt(d[a] > 0.0 ? d[a] : 0.0) * Q[j][a];
+            r[i][j] = acc;
+        }
+    out[0] = r[0][0]; out[1] = r[1][1]; out[2] = r[2][2];
+    out[3] = 0.5 * (r[0][1] + r[1][0]);
+    out[4] = 0.5 * (r[0][2] + r[2][0]);
+    out[5] = 0.5 * (r[1][2] + r[2][1]);
+}
+
+/* x = A^-1 b by Cramer's rule */
+static void solve3(const double A[3][3], const double b[3], double x[3])
+{
+    double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+               - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+               + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    for (int c = 0; c < 3; ++c) {
+        double B[3][3];
+        memcpy(B, A, sizeof(B));
+        for (int r = 0; r < 3; ++r) B[r][c] = b[r];
+        x[c] = (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1])
+              - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0])
+              + B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0])) / det;
+    }
+}
+
+/* Corrected velocity and force with a full tensor: Eqs. forcement + expandV
+ * give Lambda(s) V' = W with W = V + eps G / 2 and
+ *   Lambda(s) = I + (eps nu / 2) K^-1 + (eps F_eps s / 2) K^-1/2,  s = |V'|.
+ * The speed solves s = |Lambda(s)^-1 W|; Lambda(s) is symmetric positive
+ * definite and grows with s, so s - |Lambda(s)^-1 W| is increasing and the
+ * root lies in [0, |Lambda(0)^-1 W|]: safeguarded Newton, the derivative of
+ * |x(s)| with x = Lambda^-1 W being -x.(Lambda^-1 B x)/|x|, B = dLambda/ds. */
+static void porous_velocity_full(const orc_params *p, double eps, const double kinv[6],
+                                 const double ksq[6], double nu, const double V[3],
+                                 double Vp[3], double Fext[3])
+{
+    double Kf[3][3], Sf[3][3], A0[3][3], B[3][3], W[3];
+    double Feps = p->forchheimer ? 1.75 / sqrt(150.0 * eps * eps * eps) : 0.0;
+    sym_full(kinv, Kf);
+    sym_full(ksq, Sf);
+    for (int a = 0; a < 3; ++a) {
+        W[a] = V[a] + 0.5 * eps * p->G[a];
+        for (int b = 0; b < 3; ++b) {
+            A0[a][b] = (a == b ? 1.0 : 0.0) + 0.5 * eps * nu * Kf[a][b];
+            B[a][b] = 0.5 * eps * Feps * Sf[a][b];
+        }
+    }
+    double x[3];
+    solve3(A0, W, x);
+    double hi = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    double s = hi;
+    if (Feps > 0.0 && hi > 0.0) {
+        double lo = 0.0;
+        for (int it = 0; it < 200; ++it) {
+            double A[3][3], Bx[3], y[3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) A[a][b] = A0[a][b] + s * B[a][b];
+            solve3(A, W, x);
+            double g = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            double phi = s - g;
+            if (phi > 0.0) hi = s; else lo = s;
+            for (int a = 0; a < 3; ++a) Bx[a] = B[a][0] * x[0] + B[a][1] * x[1] + B[a][2] * x[2];
+            solve3(A, Bx, y);
+            double dg = g > 0.0 ? -(x[0] * y[0] + x[1] * y[1] + x[2] * y[2]) / g : 0.0;
+            double sn = s - phi / (1.0 - dg);
+            if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+            if (fabs(sn - s) <= 1e-16 * s || hi - lo <= 1e-16 * hi) { s = sn; break; }
+            s = sn;
+        }
+    }
+    double A[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) A[a][b] = A0[a][b] + s * B[a][b];
+    solve3(A, W, Vp);
+    double sp = sqrt(Vp[0] * Vp[0] + Vp[1] * Vp[1] + Vp[2] * Vp[2]);
+    for (int a = 0; a < 3; ++a) {
+        double kv = Kf[a][0] * Vp[0] + Kf[a][1] * Vp[1] + Kf[a][2] * Vp[2];
+        double sv = Sf[a][0] * Vp[0] + Sf[a][1] * Vp[1] + Sf[a][2] * Vp[2];
+        Fext[a] = eps * p->G[a] - eps * nu * kv - eps * Feps * sp * sv;
+    }
+}
+
 /* Equilibrium of the hydrodynamic lattice, Eqs. equilc1 and equilc2, returned
  * as deviations f^eq_i - w_i.  rho = 1 + drho.  The surface-tension part is
  * w_i A eps tau ((v.F)^2/|F| - |F|) for the moving directions and
@@ -354,7 +502,6 @@ static void collide_cell(const orc_state *s, int x, int y, int z, double t,
     const orc_params *p = &s->p;
     long i0 = cidx(s, x, y, z);
     double eps = s->eps[i0];
-    double kinv[3] = {s->kinv[i0], s->kinv[s->n + i0], s->kinv[2 * s->n + i0]};
 
     /* moments (Eqs. macros1, macros, all 19 directions) */
     double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -379,7 +526,17 @@ static void collide_cell(const orc_state *s, int x, int y, int z, double t,
     double tau = 0.5 + 3.0 * nu;
 
     double Vp[3], Fext[3];
-    porous_velocity(p, eps, kinv, nu, V, Vp, Fext);
+    if (p->full_tensor) {
+        double kinv[6], ksq[6];
+        for (int c = 0; c < 6; ++c) {
+            kinv[c] = s->kinv[c * s->n + i0];
+            ksq[c] = s->ksqrt[c * s->n + i0];
+        }
+        porous_velocity_full(p, eps, kinv, ksq, nu, V, Vp, Fext);
+    } else {
+        double kinv[3] = {s->kinv[i0], s->kinv[s->n + i0], s->kinv[2 * s->n + i0]};
+        porous_velocity(p, eps, kinv, nu, V, Vp, Fext);
+    }
 
     double F[3] = {0.0, 0.0, 0.0};
     if (p->physics == PHYS_IMMISCIBLE) colour_gradient(s, x, y, z, F);
@@ -499,10 +656,21 @@ void orc_porous_velocity(const orc_params *p, double eps, const double kinv[3], 
     porous_velocity(p, eps, kinv, nu, V, Vp, Fext);
 }
 
+/* full-tensor forms for the tests: K^-1/2 of one cell, and V', F^ext */
+void orc_sym_sqrt(const double k[6], double out[6]) { sym_sqrt(k, out); }
+
+void orc_porous_velocity_full(const orc_params *p, double eps, const double kinv[6], double nu,
+                              const double V[3], double Vp[3], double Fext[3])
+{
+    double ksq[6];
+    sym_sqrt(kinv, ksq);
+    porous_velocity_full(p, eps, kinv, ksq, nu, V, Vp, Fext);
+}
+
 void orc_destroy(orc_state *s)
 {
     if (!s) return;
-    free(s->eps); free(s->kinv); free(s->type); free(s->tface);
+    free(s->eps); free(s->kinv); free(s->ksqrt); free(s->type); free(s->tface);
     free(s->f[0]); free(s->f[1]); free(s->h[0]); free(s->h[1]);
     free(s->rho); free(s->vel); free(s->conc); free(s->vsnap); free(s->rho1);
     free(s);
@@ -511,7 +679,7 @@ void orc_destroy(orc_state *s)
 /* Create the state and apply the initial conditions (flowchart, first three
  * boxes): f = f^eq(rho0, V' := V0, F, eps, tau(C0, 0)); h = h^eq(eps C0,
  * V0 + D grad(eps)/eps); g = C0 f.  Arrays are FP64, idx = x + nx (y + ny z);
- * kinv and vel0 hold 3 planes; solid (may be NULL) marks obstacle cells,
+ * kinv holds 3 planes (6 with full_tensor), vel0 3 planes; solid (may be NULL) marks obstacle cells,
  * which carry no state and reflect the populations that stream into them.
  * Returns NULL on allocation failure.                                      */
 orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv,
@@ -525,7 +693,9 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
     s->n = (long)p->nx * p->ny * p->nz;
     long n = s->n;
     s->eps = malloc(sizeof(double) * n);
-    s->kinv = malloc(sizeof(double) * 3 * n);
+    const int nk = p->full_tensor ? 6 : 3;
+    s->kinv = malloc(sizeof(double) * nk * n);
+    s->ksqrt = p->full_tensor ? malloc(sizeof(double) * 6 * n) : NULL;
     s->type = malloc(n);
     s->tface = malloc(n);
     s->f[0] = calloc((size_t)NQ * n, sizeof(double));
@@ -535,10 +705,18 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
     s->conc = calloc(n, sizeof(double));
     s->vsnap = calloc(3 * n, sizeof(double));
     s->rho1 = calloc(n, sizeof(double));
-    if (!s->eps || !s->kinv || !s->type || !s->tface || !s->f[0] || !s->h[0] || !s->rho ||
+    if (!s->eps || !s->kinv || (p->full_tensor && !s->ksqrt) || !s->type || !s->tface || !s->f[0] || !s->h[0] || !s->rho ||
         !s->vel || !s->conc || !s->vsnap || !s->rho1) { orc_destroy(s); return NULL; }
     memcpy(s->eps, eps, sizeof(double) * n);
-    memcpy(s->kinv, kinv, sizeof(double) * 3 * n);
+    memcpy(s->kinv, kinv, sizeof(double) * nk * n);
+    if (p->full_tensor) {
+        for (long i = 0; i < n; ++i) {
+            double k[6], r[6];
+            for (int c = 0; c < 6; ++c) k[c] = kinv[c * n + i];
+            sym_sqrt(k, r);
+            for (int c = 0; c < 6; ++c) s->ksqrt[c * n + i] = r[c];
+        }
+    }
     classify(s, solid);
     s->cur = 0;
 

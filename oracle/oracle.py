@@ -31,6 +31,7 @@ class OrcParams(C.Structure):
         ("face_kind", C.c_int * 6),
         ("face_rho", C.c_double * 6), ("face_conc", C.c_double * 6), ("face_angle", C.c_double * 6),
         ("solid_angle", C.c_double),
+        ("full_tensor", C.c_int),
     ]
 
 
@@ -64,6 +65,8 @@ def lib():
         L.orc_solve_speed.argtypes = [dp, dp, dp]
         L.orc_solve_speed.restype = C.c_double
         L.orc_porous_velocity.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
+        L.orc_porous_velocity_full.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
+        L.orc_sym_sqrt.argtypes = [dp, dp]
         _lib = L
     return _lib
 
@@ -93,6 +96,7 @@ def params_from_problem(p) -> OrcParams:
     o.face_conc = (C.c_double * 6)(*[float(f.conc) for f in p.faces])
     o.face_angle = (C.c_double * 6)(*[float(f.angle) for f in p.faces])
     o.solid_angle = float(p.solid_angle)
+    o.full_tensor = int(p.kinv is not None and np.asarray(p.kinv).shape[0] == 6)
     return o
 
 
@@ -133,12 +137,22 @@ def viscosity(problem, C_, t):
 
 
 def porous_velocity(problem, eps, kinv, nu, V):
+    """(V', F^ext) of one cell; kinv has 3 (diagonal) or 6 ({xx,yy,zz,xy,xz,yz})
+    components."""
     prm = params_from_problem(problem)
     Vp = np.zeros(3)
     Fx = np.zeros(3)
-    lib().orc_porous_velocity(C.byref(prm), float(eps), _dp(_vec(kinv)), float(nu), _dp(_vec(V)),
-                              _dp(Vp), _dp(Fx))
+    k = _vec(kinv)
+    fn = lib().orc_porous_velocity_full if k.size == 6 else lib().orc_porous_velocity
+    fn(C.byref(prm), float(eps), _dp(k), float(nu), _dp(_vec(V)), _dp(Vp), _dp(Fx))
     return Vp, Fx
+
+
+def sym_sqrt(k6):
+    """The oracle's K^-1/2 of a symmetric tensor {xx,yy,zz,xy,xz,yz}."""
+    out = np.zeros(6)
+    lib().orc_sym_sqrt(_dp(_vec(k6)), _dp(out))
+    return out
 
 
 class Oracle:

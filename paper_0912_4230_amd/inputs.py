@@ -57,7 +57,7 @@ class Problem:
     beta: float = 0.7       # recolouring strength
     faces: List[Face] = dataclasses.field(default_factory=lambda: [Face() for _ in range(6)])
     eps: Optional[np.ndarray] = None    # (nz,ny,nx)
-    kinv: Optional[np.ndarray] = None   # (3,nz,ny,nx)
+    kinv: Optional[np.ndarray] = None   # (3,nz,ny,nx) diagonal, or (6,nz,ny,nx) full {xx,yy,zz,xy,xz,yz}
     rho0: Optional[np.ndarray] = None   # (nz,ny,nx)
     vel0: Optional[np.ndarray] = None   # (3,nz,ny,nx)
     c0: Optional[np.ndarray] = None     # (nz,ny,nx)
@@ -86,7 +86,11 @@ class Problem:
     def uniform_medium(self) -> bool:
         e = self.eps
         k = self.kinv
-        return bool(np.all(e == e.flat[0]) and all(np.all(k[a] == k[a].flat[0]) for a in range(3)))
+        return bool(np.all(e == e.flat[0]) and all(np.all(k[a] == k[a].flat[0]) for a in range(k.shape[0])))
+
+    @property
+    def full_tensor(self) -> bool:
+        return self.kinv is not None and np.asarray(self.kinv).shape[0] == 6
 
 
 # --------------------------------------------------------------------------
@@ -159,6 +163,41 @@ def spruce_medium(shape, seed: int = 0, ratio: float = 100.0, origin=(0, 0, 0),
     return eps, kinv
 
 
+def inclined_spruce_medium(shape, seed: int = 0, ratio: float = 100.0, angle_deg: float = 45.0,
+                           origin=(0, 0, 0), eps_lo: float = 0.4, eps_hi: float = 0.8,
+                           period: float = 32.0, k_ref: float = 1e-2, sigma: float = 0.3):
+    """The spruce-like medium with its annual rings inclined by `angle_deg` in
+    the x-y plane (the rotated permeability of Eq. Ktensor): radial axis
+    n = (cos a, sin a, 0), longitudinal axis l = (-sin a, cos a, 0),
+    tangential axis z.  Porosity follows the ring coordinate r = n.x (global
+    cell coordinates); K = K_L (n n^T / R + l l^T + z z^T / R) with
+    K_L = K_ref kappa(eps)/kappa(eps_mid) exp(sigma xi), so
+    K^-1 = (R n n^T + l l^T + R z z^T) / K_L.  At angle 0 this is
+    `spruce_medium` written as a full tensor.  Returns (eps (nz,ny,nx),
+    kinv (6,nz,ny,nx) = {xx, yy, zz, xy, xz, yz}) in float64."""
+    nx, ny, nz = shape
+    ox, oy, oz = origin
+    a = math.radians(angle_deg)
+    c, sn = math.cos(a), math.sin(a)
+    Z, Y, X = np.meshgrid(np.arange(nz, dtype=np.int64) + oz, np.arange(ny, dtype=np.int64) + oy,
+                          np.arange(nx, dtype=np.int64) + ox, indexing="ij")
+    r = c * X + sn * Y
+    mid = 0.5 * (eps_lo + eps_hi)
+    amp = 0.5 * (eps_hi - eps_lo)
+    eps = mid + amp * np.sin(2.0 * math.pi * r / period)
+    xi = cell_normal(seed, X, Y, Z)
+    kl = k_ref * kappa(eps) / kappa(mid) * np.exp(sigma * xi)
+    ikl = 1.0 / kl
+    kinv = np.empty((6, nz, ny, nx))
+    kinv[0] = ratio * ikl * (c * c) + ikl * (sn * sn)
+    kinv[1] = ratio * ikl * (sn * sn) + ikl * (c * c)
+    kinv[2] = ratio * ikl
+    kinv[3] = (ratio - 1.0) * ikl * (c * sn)
+    kinv[4] = 0.0
+    kinv[5] = 0.0
+    return eps, kinv
+
+
 # --------------------------------------------------------------------------
 # problems shaped like the paper's workloads
 
@@ -194,13 +233,17 @@ P_EXT = 0.0441  # applied pressure of the penetration example, Sec. 5.5
 
 
 def miscible(shape=(256, 256, 256), seed=0, ratio=100.0, origin=(0, 0, 0), D=0.05,
-             p_ext=P_EXT, reservoirs=True) -> Problem:
+             p_ext=P_EXT, reservoirs=True, ring_angle=None) -> Problem:
     """Miscible mixture in the spruce-like medium: hydrodynamic lattice plus the
     solute lattice (diffusivity D), hardening viscosity, Darcy + Forchheimer
     drag, inlet reservoir at x = 0 with rho = 1 + 3 p_ext and C = 1, outlet
-    reservoir at x = nx-1 with rho = 1 and C = 0, periodic in y and z."""
+    reservoir at x = nx-1 with rho = 1 and C = 0, periodic in y and z.  With
+    `ring_angle` (degrees) the rings are inclined and K^-1 is a full tensor."""
     nx, ny, nz = shape
-    eps, kinv = spruce_medium(shape, seed=seed, ratio=ratio, origin=origin)
+    if ring_angle is None:
+        eps, kinv = spruce_medium(shape, seed=seed, ratio=ratio, origin=origin)
+    else:
+        eps, kinv = inclined_spruce_medium(shape, seed=seed, ratio=ratio, angle_deg=ring_angle, origin=origin)
     faces = [Face() for _ in range(6)]
     if reservoirs:
         faces[0] = Face(kind=RESERVOIR, rho=1.0 + 3.0 * p_ext, conc=1.0)
