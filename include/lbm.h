@@ -6,8 +6,9 @@
  * using a Lattice Boltzmann Model" (arXiv:0912.4230) on one GPU:
  *   - a D3Q19 hydrodynamic lattice with BGK collision and forcing terms for
  *     the porous medium (Sec. 2.1, Eqs. lbe2, coeffforce1, forcement,
- *     expandV, expandVsub, equilc1, equilc2): porosity eps, a diagonal
- *     anisotropic permeability K, body force G, Darcy drag and (optionally) a
+ *     expandV, expandVsub, equilc1, equilc2): porosity eps, an anisotropic
+ *     permeability K (diagonal, or a full symmetric tensor), body force G,
+ *     Darcy drag and (optionally) a
  *     Forchheimer drag, with a local viscosity nu(C, t) for hardening fluids
  *     (family of Eq. nuall);
  *   - a second D3Q19 lattice that is either the solute of a miscible mixture
@@ -120,6 +121,9 @@ typedef struct {
                                    32-bit link word per cell */
     double solid_contact_angle_deg;  /* two-fluid: contact angle of fluid 1 on the
                                    obstacle cells of the mask */
+    int full_tensor;            /* 1: lbm_medium.kinv holds a full symmetric K^-1 per cell
+                                   (the rotated tensor of Eq. Ktensor), 6 planes
+                                   {xx, yy, zz, xy, xz, yz}; 0: the diagonal, 3 planes */
 } lbm_desc;
 
 /* Medium and initial fields (flowchart of Sec. 4: set rho, V, C, the
@@ -129,7 +133,9 @@ typedef struct {
  * passed the call (lbm_set_medium synchronises before returning). */
 typedef struct {
     const void *eps;            /* ncell values in (0, 1]; NULL: eps_uniform */
-    const void *kinv;           /* 3 planes: 1/K_xx, 1/K_yy, 1/K_zz >= 0; NULL: kinv_uniform */
+    const void *kinv;           /* 3 planes: 1/K_xx, 1/K_yy, 1/K_zz >= 0 (full_tensor: 6 planes
+                                   {xx, yy, zz, xy, xz, yz} of a positive semi-definite
+                                   K^-1); NULL: kinv_uniform (diagonal) */
     const void *rho0;           /* ncell initial densities > 0; NULL: 1 */
     const void *vel0;           /* 3 planes, initial velocity V' ; NULL: 0 */
     const void *c0;             /* ncell initial concentrations; NULL: 0 */
@@ -138,7 +144,12 @@ typedef struct {
     const unsigned char *solid; /* ncell bytes, nonzero = obstacle cell; only with
                                    desc.solid_mask = 1 (NULL there: no obstacles) */
 } lbm_medium;
-/* Obstacle cells of the mask are solid exactly like the cells of a wall face
+/* A full tensor enters Eqs. forcement and expandV as the matrix K^-1 and the
+ * Forchheimer drag as its positive square root K^-1/2 (they share the
+ * eigenframe of K); lbm_set_medium stores each cell's eigenframe (a unit
+ * quaternion) and eigenvalues, 7 planes in the workspace.
+ *
+ * Obstacle cells of the mask are solid exactly like the cells of a wall face
  * (Sec. 4: bounce-back on every link into them, no state, moments read 0);
  * a cell on a wall face is a wall cell, else a masked cell is an obstacle,
  * else a cell on a reservoir face belongs to the reservoir.  Their porosity

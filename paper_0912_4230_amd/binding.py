@@ -43,6 +43,7 @@ class lbm_desc(C.Structure):
         ("diag_every", C.c_int),
         ("solid_mask", C.c_int),
         ("solid_contact_angle_deg", C.c_double),
+        ("full_tensor", C.c_int),
     ]
 
 

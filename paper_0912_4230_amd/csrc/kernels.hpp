@@ -60,6 +60,7 @@ struct LatDev {
     int physics;
     int forch, eps_grad;
     int uniform_eps, uniform_kinv;
+    int full_tensor;            // K^-1 per cell as frame quaternion (4 planes) + eigenvalues (3 planes)
     uint32_t wall_faces, res_faces;   // bit f: face f (-x,+x,-y,+y,-z,+z) is a wall / a reservoir
     double eps_u, kinv_u[3];
     double G[3];
@@ -590,11 +591,12 @@ __device__ inline void recolour(R *g, const R *d, R C, const R Cw[3], const R rw
 }
 
 // Porous velocity and force (Eqs. forcement, expandV, expandVsub with eps on
-// G, diagonal K, optional Forchheimer drag).
+// G, diagonal K, optional Forchheimer drag).  G is the body force in the
+// frame of kinv.
 template <class R>
-__device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R nu, const R V[3], R u[3], R Fx[3])
+__device__ inline void porous_core(const LatDev *L, const R G[3], R eps, const R kinv[3], R nu, const R V[3],
+                                   R u[3], R Fx[3])
 {
-    const R G[3] = {R(L->G[0]), R(L->G[1]), R(L->G[2])};
     R W[3], lam[3], ilam[3], mu[3], sk[3];
     R Feps = R(0);
     const bool forch = L->forch != 0;
@@ -619,6 +621,59 @@ __device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R n
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         Fx[a] = eps * G[a] - eps * nu * kinv[a] * u[a] - eps * Feps * sp * sk[a] * u[a];
+}
+
+template <class R>
+__device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R nu, const R V[3], R u[3], R Fx[3])
+{
+    const R G[3] = {R(L->G[0]), R(L->G[1]), R(L->G[2])};
+    porous_core<R>(L, G, eps, kinv, nu, V, u, Fx);
+}
+
+// Rotation matrix (columns: the eigenvectors of K^-1) of a unit quaternion
+// (w, x, y, z).
+template <class R>
+__device__ inline void quat_matrix(const R q[4], R M[3][3])
+{
+    const R w = q[0], x = q[1], y = q[2], z = q[3];
+    M[0][0] = R(1) - R(2) * (y * y + z * z);
+    M[0][1] = R(2) * (x * y - z * w);
+    M[0][2] = R(2) * (x * z + y * w);
+    M[1][0] = R(2) * (x * y + z * w);
+    M[1][1] = R(1) - R(2) * (x * x + z * z);
+    M[1][2] = R(2) * (y * z - x * w);
+    M[2][0] = R(2) * (x * z - y * w);
+    M[2][1] = R(2) * (y * z + x * w);
+    M[2][2] = R(1) - R(2) * (x * x + y * y);
+}
+
+// Full tensor K^-1 = Q diag(mu) Q^T: K^-1 and K^-1/2 share the frame Q, so in
+// that frame Eqs. forcement and expandV (with the Forchheimer drag) are the
+// diagonal ones.  V and G are rotated in, V' and F^ext rotated back.
+template <class R>
+__device__ inline void porous_force_frame(const LatDev *L, R eps, const R q[4], const R mu[3], R nu, const R V[3],
+                                          R u[3], R Fx[3])
+{
+    R M[3][3];
+    quat_matrix<R>(q, M);
+    R Vr[3], Gr[3];
+    const R G[3] = {R(L->G[0]), R(L->G[1]), R(L->G[2])};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Vr[a] = M[0][a] * V[0] + M[1][a] * V[1] + M[2][a] * V[2];
+        Gr[a] = M[0][a] * G[0] + M[1][a] * G[1] + M[2][a] * G[2];
+    }
+    R ur[3], Fr[3];
+    porous_core<R>(L, Gr, eps, mu, nu, Vr, ur, Fr);
+    // F^ext = eps G - Q (drag in the frame); eps G exactly, the drag rotated back
+    R Dr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Dr[a] = eps * Gr[a] - Fr[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a] = M[a][0] * ur[0] + M[a][1] * ur[1] + M[a][2] * ur[2];
+        Fx[a] = eps * G[a] - (M[a][0] * Dr[0] + M[a][1] * Dr[1] + M[a][2] * Dr[2]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -675,8 +730,9 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 
 // ---------------------------------------------------------------------------
 // The step kernel: pull-stream both lattices, moments, viscosity, porous
-// force, (colour gradient), collide, write the other copy.
-template <int PHYS, class S>
+// force, (colour gradient), collide, write the other copy.  FT: every lattice
+// of the launch has a full permeability tensor (eigenframe form).
+template <int PHYS, class S, bool FT = false>
 __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
@@ -721,16 +777,6 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
         const R V[3] = {jx * irho, jy * irho, jz * irho};
 
         const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
-        R kinv[3];
-        if (L->uniform_kinv) {
-            kinv[0] = R(L->kinv_u[0]);
-            kinv[1] = R(L->kinv_u[1]);
-            kinv[2] = R(L->kinv_u[2]);
-        } else {
-            kinv[0] = ldg<R>(L->kinv, idx);
-            kinv[1] = ldp<R>(L->kinv, ncell, 1, idx);
-            kinv[2] = ldp<R>(L->kinv, ncell, 2, idx);
-        }
         const R ie = rcp(eps);
 
         R sh = 0, rho1 = 0, C = 0;
@@ -755,7 +801,25 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
         const R omega = rcp(tau);
 
         R u[3], Fx[3];
-        porous_force<R>(L, eps, kinv, nu, V, u, Fx);
+        if constexpr (FT) {
+            const R q[4] = {ldg<R>(L->kinv, idx), ldp<R>(L->kinv, ncell, 1, idx), ldp<R>(L->kinv, ncell, 2, idx),
+                            ldp<R>(L->kinv, ncell, 3, idx)};
+            const R mu[3] = {ldp<R>(L->kinv, ncell, 4, idx), ldp<R>(L->kinv, ncell, 5, idx),
+                             ldp<R>(L->kinv, ncell, 6, idx)};
+            porous_force_frame<R>(L, eps, q, mu, nu, V, u, Fx);
+        } else {
+            R kinv[3];
+            if (L->uniform_kinv) {
+                kinv[0] = R(L->kinv_u[0]);
+                kinv[1] = R(L->kinv_u[1]);
+                kinv[2] = R(L->kinv_u[2]);
+            } else {
+                kinv[0] = ldg<R>(L->kinv, idx);
+                kinv[1] = ldp<R>(L->kinv, ncell, 1, idx);
+                kinv[2] = ldp<R>(L->kinv, ncell, 2, idx);
+            }
+            porous_force<R>(L, eps, kinv, nu, V, u, Fx);
+        }
 
         R F[3] = {0, 0, 0};
         R Fn = 0, iFn = 0, st = 0;
@@ -932,6 +996,106 @@ __global__ __launch_bounds__(BLOCK) void k_links(const LatDev *L, const unsigned
     links[idx] = w;
 }
 
+// Eigen-decomposition of a symmetric 3x3 matrix A = V diag(d) V^T by the
+// classical Jacobi method (rotate away the largest off-diagonal entry until
+// all are negligible; Golub and Van Loan, Matrix Computations, Sec. 8.5).
+__device__ inline void sym_eig3(double A[3][3], double d[3], double V[3][3])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int it = 0; it < 64; ++it) {
+        int p = 0, q = 1;
+        double big = fabs(A[0][1]);
+        if (fabs(A[0][2]) > big) { p = 0; q = 2; big = fabs(A[0][2]); }
+        if (fabs(A[1][2]) > big) { p = 1; q = 2; big = fabs(A[1][2]); }
+        if (big == 0.0 || big <= 1e-18 * (fabs(A[p][p]) + fabs(A[q][q]))) break;
+        const double h = A[q][q] - A[p][p];
+        const double th = 0.5 * h / A[p][q];
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < 3; ++k) {
+            const double kp = A[k][p], kq = A[k][q];
+            A[k][p] = c * kp - sn * kq;
+            A[k][q] = sn * kp + c * kq;
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double pk = A[p][k], qk = A[q][k];
+            A[p][k] = c * pk - sn * qk;
+            A[q][k] = sn * pk + c * qk;
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double vp = V[k][p], vq = V[k][q];
+            V[k][p] = c * vp - sn * vq;
+            V[k][q] = sn * vp + c * vq;
+        }
+    }
+    for (int i = 0; i < 3; ++i) d[i] = A[i][i];
+}
+
+// Full permeability tensor, set-up: K^-1 given as 6 planes {xx, yy, zz, xy,
+// xz, yz} becomes the unit quaternion of its eigenframe (planes 0-3 of the
+// lattice's K^-1 section, a proper rotation) and its eigenvalues (planes 4-6),
+// in FP64 before rounding to the real type.  Non-solid cells with a
+// non-finite or not positive semi-definite K^-1 set the error flag.
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_frame(const LatDev *L, const R *kin)
+{
+    const uint32_t ncell = L->ncell;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= ncell) return;
+    const size_t n = ncell;
+    double A[3][3], k[6];
+    bool fin = true;
+    for (int c = 0; c < 6; ++c) {
+        k[c] = double(kin[c * n + idx]);
+        fin = fin && isfinite(k[c]);
+    }
+    if (!fin) for (int c = 0; c < 6; ++c) k[c] = 0.0;
+    A[0][0] = k[0]; A[1][1] = k[1]; A[2][2] = k[2];
+    A[0][1] = A[1][0] = k[3];
+    A[0][2] = A[2][0] = k[4];
+    A[1][2] = A[2][1] = k[5];
+    double d[3], V[3][3];
+    sym_eig3(A, d, V);
+    const double dmax = fmax(fabs(d[0]), fmax(fabs(d[1]), fabs(d[2])));
+    bool psd = true;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] < -1e-12 * dmax) psd = false;
+        d[a] = fmax(d[a], 0.0);
+    }
+    // proper rotation: flip the last eigenvector if det V = -1
+    const double det = V[0][0] * (V[1][1] * V[2][2] - V[1][2] * V[2][1]) -
+                       V[0][1] * (V[1][0] * V[2][2] - V[1][2] * V[2][0]) +
+                       V[0][2] * (V[1][0] * V[2][1] - V[1][1] * V[2][0]);
+    if (det < 0.0)
+        for (int r = 0; r < 3; ++r) V[r][2] = -V[r][2];
+    // quaternion of the rotation V (Shepperd's branch on the largest term)
+    double w, x, y, z;
+    const double tr = V[0][0] + V[1][1] + V[2][2];
+    if (tr > 0.0) {
+        const double S = 2.0 * sqrt(tr + 1.0);
+        w = 0.25 * S; x = (V[2][1] - V[1][2]) / S; y = (V[0][2] - V[2][0]) / S; z = (V[1][0] - V[0][1]) / S;
+    } else if (V[0][0] > V[1][1] && V[0][0] > V[2][2]) {
+        const double S = 2.0 * sqrt(1.0 + V[0][0] - V[1][1] - V[2][2]);
+        w = (V[2][1] - V[1][2]) / S; x = 0.25 * S; y = (V[0][1] + V[1][0]) / S; z = (V[0][2] + V[2][0]) / S;
+    } else if (V[1][1] > V[2][2]) {
+        const double S = 2.0 * sqrt(1.0 + V[1][1] - V[0][0] - V[2][2]);
+        w = (V[0][2] - V[2][0]) / S; x = (V[0][1] + V[1][0]) / S; y = 0.25 * S; z = (V[1][2] + V[2][1]) / S;
+    } else {
+        const double S = 2.0 * sqrt(1.0 + V[2][2] - V[0][0] - V[1][1]);
+        w = (V[1][0] - V[0][1]) / S; x = (V[0][2] + V[2][0]) / S; y = (V[1][2] + V[2][1]) / S; z = 0.25 * S;
+    }
+    const double qn = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    const double out[7] = {w * qn, x * qn, y * qn, z * qn, d[0], d[1], d[2]};
+    for (int c = 0; c < 7; ++c) stp<R>(L->kinv, ncell, c, idx, R(out[c]));
+    const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+    const int zc = idx / nxy;
+    const uint32_t r = idx - uint32_t(zc) * nxy;
+    const int yc = r / nx, xc = r - uint32_t(yc) * nx;
+    int face;
+    if ((!fin || !psd) && cell_type(L, xc, yc, zc, link_word(L, idx), face) != CELL_SOLID) *L->err = 1;
+}
+
 // colour field of the initial state (two-fluid): C0 rho0 in fluid cells.
 template <class R>
 __global__ __launch_bounds__(BLOCK) void k_init_colour(const InitArgs<R> ia)
@@ -973,7 +1137,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
 
     const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
     R kinv[3];
-    for (int a = 0; a < 3; ++a) kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : ldp<R>(L->kinv, ncell, a, idx);
+    // full tensor: the eigenvalue planes (4-6) after the frame quaternion
+    for (int a = 0; a < 3; ++a)
+        kinv[a] = L->uniform_kinv ? R(L->kinv_u[a]) : ldp<R>(L->kinv, ncell, L->full_tensor ? 4 + a : a, idx);
     const R rho0 = ia.rho0 ? ia.rho0[idx] : R(1);
     R u0[3];
     for (int a = 0; a < 3; ++a) u0[a] = ia.vel0 ? ia.vel0[a * n + idx] : R(0);

@@ -91,6 +91,7 @@ bool valid_desc(const lbm_desc *d)
     if (d->physics == LBM_MISCIBLE && (!(d->tau_d > 0.5) || !is_fin(d->tau_d))) return false;
     if (d->diag_every < 0) return false;
     if (d->solid_mask != 0 && d->solid_mask != 1) return false;
+    if (d->full_tensor != 0 && d->full_tensor != 1) return false;
     if (d->solid_mask && d->physics == LBM_IMMISCIBLE && !is_fin(d->solid_contact_angle_deg)) return false;
     return true;
 }
@@ -107,7 +108,7 @@ Layout layout(const lbm_desc *d)
     L.diag = o;      o = align_up(o + 8 * sizeof(double));
     L.partials = o;  o = align_up(o + nb * NPART * sizeof(double));
     L.eps = o;       o = align_up(o + n * rb);
-    L.kinv = o;      o = align_up(o + 3 * n * rb);
+    L.kinv = o;      o = align_up(o + (d->full_tensor ? 7 : 3) * n * rb);
     L.mom = o;       o = align_up(o + 5 * n * rb);
     L.rho1 = o;      if (d->physics == LBM_IMMISCIBLE) o = align_up(o + n * rb);
     L.links = o;     if (d->solid_mask) o = align_up(o + n * sizeof(uint32_t));
@@ -174,10 +175,10 @@ using Launch = void (*)(const BatchArgs &, int blocks, hipStream_t);
 // SIMD, which measured 2-3% slower on the FP32 miscible and two-fluid steps.
 constexpr size_t STEP_LDS_RESERVE = 33 * 1024;
 
-template <int P, class S>
+template <int P, class S, bool FT>
 void launch_step(const BatchArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<P, S>), dim3(blocks), dim3(BLOCK), STEP_LDS_RESERVE, s, a);
+    hipLaunchKernelGGL((k_step<P, S, FT>), dim3(blocks), dim3(BLOCK), STEP_LDS_RESERVE, s, a);
 }
 
 template <class S>
@@ -186,25 +187,31 @@ void launch_colour(const BatchArgs &a, int blocks, hipStream_t s)
     hipLaunchKernelGGL((k_colour<S>), dim3(blocks), dim3(BLOCK), 0, s, a);
 }
 
-template <int P>
+template <int P, bool FT>
 Launch step_for_storage(int storage)
 {
     switch (storage) {
-    case LBM_F64: return launch_step<P, double>;
-    case LBM_F32: return launch_step<P, float>;
-    case LBM_BF16_DEV: return launch_step<P, bf16_t>;
-    case LBM_F16_DEV: return launch_step<P, f16_t>;
-    case LBM_BF16_SPLIT: return launch_step<P, bf16s_t>;
-    default: return launch_step<P, f16s_t>;
+    case LBM_F64: return launch_step<P, double, FT>;
+    case LBM_F32: return launch_step<P, float, FT>;
+    case LBM_BF16_DEV: return launch_step<P, bf16_t, FT>;
+    case LBM_F16_DEV: return launch_step<P, f16_t, FT>;
+    case LBM_BF16_SPLIT: return launch_step<P, bf16s_t, FT>;
+    default: return launch_step<P, f16s_t, FT>;
     }
 }
 
-Launch step_launcher(int physics, int storage)
+template <int P>
+Launch step_for_tensor(int storage, bool full_tensor)
+{
+    return full_tensor ? step_for_storage<P, true>(storage) : step_for_storage<P, false>(storage);
+}
+
+Launch step_launcher(int physics, int storage, bool full_tensor)
 {
     switch (physics) {
-    case LBM_SINGLE: return step_for_storage<PH_SINGLE>(storage);
-    case LBM_MISCIBLE: return step_for_storage<PH_MISCIBLE>(storage);
-    default: return step_for_storage<PH_IMMISCIBLE>(storage);
+    case LBM_SINGLE: return step_for_tensor<PH_SINGLE>(storage, full_tensor);
+    case LBM_MISCIBLE: return step_for_tensor<PH_MISCIBLE>(storage, full_tensor);
+    default: return step_for_tensor<PH_IMMISCIBLE>(storage, full_tensor);
     }
 }
 
@@ -255,7 +262,8 @@ bool diag_step(const lbm_sim *h, long long t, bool last)
     return last || (h->d.diag_every > 0 && t % h->d.diag_every == 0);
 }
 
-// One batched step for lattices hs[0..n) of the same physics and storage:
+// One batched step for lattices hs[0..n) of the same physics, storage and
+// permeability form (diagonal or full tensor):
 // [colour pass,] step kernel, [diagnostics second stage].
 lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
 {
@@ -281,7 +289,7 @@ lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
     a.total_blocks = total;
     const lbm_sim *h0 = hs[0];
     if (h0->d.physics == LBM_IMMISCIBLE) colour_launcher(h0->d.storage)(a, total, h0->stream);
-    step_launcher(h0->d.physics, h0->d.storage)(a, total, h0->stream);
+    step_launcher(h0->d.physics, h0->d.storage, h0->host.full_tensor != 0)(a, total, h0->stream);
     if (ndiag) {
         diag.n = ndiag;
         hipLaunchKernelGGL(k_diag_final, dim3(ndiag), dim3(BLOCK), 0, h0->stream, diag);
@@ -399,6 +407,7 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     LatDev &D = h->host;
     D.uniform_eps = m->eps ? 0 : 1;
     D.uniform_kinv = m->kinv ? 0 : 1;
+    D.full_tensor = (h->d.full_tensor && m->kinv) ? 1 : 0;
     D.eps_u = m->eps_uniform;
     for (int a = 0; a < 3; ++a) D.kinv_u[a] = m->kinv_uniform[a];
     if (!m->eps && !(m->eps_uniform > 0.0 && m->eps_uniform <= 1.0)) return LBM_EINVAL;
@@ -411,10 +420,20 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     static const int zero = 0;
     if ((st = dev_err(hipMemcpyAsync(D.err, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream)))) return st;
     if (m->eps && (st = dev_err(hipMemcpyAsync(D.eps, m->eps, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
-    if (m->kinv && (st = dev_err(hipMemcpyAsync(D.kinv, m->kinv, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    if (m->kinv && !D.full_tensor &&
+        (st = dev_err(hipMemcpyAsync(D.kinv, m->kinv, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream))))
+        return st;
     if (D.links) {
         uint32_t *links = static_cast<uint32_t *>(const_cast<void *>(D.links));
         hipLaunchKernelGGL(k_links, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev, m->solid, links);
+    }
+    if (D.full_tensor) {
+        if (h->d.storage == LBM_F64)
+            hipLaunchKernelGGL(k_frame<double>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev,
+                               static_cast<const double *>(m->kinv));
+        else
+            hipLaunchKernelGGL(k_frame<float>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev,
+                               static_cast<const float *>(m->kinv));
     }
     switch (h->d.physics) {
     case LBM_SINGLE: init_for_storage<PH_SINGLE>(h, m, h->nblocks); break;
@@ -471,13 +490,15 @@ lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n)
     lbm_sim *grp[MAXB];
     bool last[MAXB];
     for (int s = 0; s < maxs; ++s) {
-        // group the lattices still running by (physics, storage)
-        for (int phys = 0; phys < 3; ++phys)
-            for (int stg = 0; stg < 4; ++stg) {
+        // group the lattices still running by (physics, storage, permeability form)
+        for (int phys = LBM_SINGLE; phys <= LBM_IMMISCIBLE; ++phys)
+            for (int grp_key = 0; grp_key < 2 * (LBM_F16_SPLIT + 1); ++grp_key) {
+                const int stg = grp_key >> 1, ft = grp_key & 1;
                 int k = 0;
                 for (int i = 0; i < n; ++i) {
                     lbm_sim *h = hs[i];
-                    if (s >= nsteps[i] || h->d.physics != phys || h->d.storage != stg) continue;
+                    if (s >= nsteps[i] || h->d.physics != phys || h->d.storage != stg || h->host.full_tensor != ft)
+                        continue;
                     grp[k] = h;
                     last[k] = s + 1 == nsteps[i];
                     if (++k == MAXB) {

@@ -35,6 +35,7 @@ def make_desc(p: I.Problem, storage: int = B.LBM_F32, diag_every: int = 0) -> B.
     d.diag_every = int(diag_every)
     d.solid_mask = int(p.solid is not None)
     d.solid_contact_angle_deg = float(p.solid_angle)
+    d.full_tensor = int(p.full_tensor)
     return d
 
 
@@ -85,7 +86,8 @@ class Simulation:
         m = B.lbm_medium()
         keep = []
         eps_u = bool(uniform_medium and np.all(p.eps == p.eps.flat[0]))
-        kinv_u = bool(uniform_medium and all(np.all(p.kinv[a] == p.kinv[a].flat[0]) for a in range(3)))
+        kinv_u = bool(uniform_medium and not p.full_tensor and
+                      all(np.all(p.kinv[a] == p.kinv[a].flat[0]) for a in range(3)))
         if eps_u:
             m.eps = None
             m.eps_uniform = float(p.eps.flat[0])

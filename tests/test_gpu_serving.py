@@ -75,3 +75,31 @@ def test_batch_of_different_shapes_matches_single_steps():
         b.close()
     for s in a:
         s.close()
+
+
+def test_batch_covers_every_storage_and_tensor_form():
+    """lbm_step_batch steps lattices of every storage mode and of both
+    permeability forms (each group its own launch) exactly like lbm_step."""
+    import torch
+    from paper_0912_4230_amd.sim import Simulation, step_batch
+    probs, storages = [], []
+    for i, st in enumerate(("f64", "f32", "bf16", "f16", "bf16s", "f16s")):
+        probs.append(I.miscible(shape=(17, 11, 9), seed=20 + i))
+        storages.append(st)
+    probs.append(I.miscible(shape=(15, 13, 10), seed=30, ring_angle=45.0))
+    storages.append("f32")
+    probs.append(I.miscible(shape=(15, 13, 10), seed=31, ring_angle=30.0))
+    storages.append("bf16s")
+    steps = [9, 12, 7, 5, 11, 8, 10, 6]
+    a = [Simulation(p, storage=st) for p, st in zip(probs, storages)]
+    step_batch(a, steps)
+    for p, st, n, s in zip(probs, storages, steps, a):
+        b = Simulation(p, storage=st)
+        b.step(n)
+        assert s.steps_done == n
+        ra, va, ca, _ = s.moments()
+        rb, vb, cb, _ = b.moments()
+        assert torch.equal(ra, rb) and torch.equal(va, vb) and torch.equal(ca, cb), st
+        b.close()
+    for s in a:
+        s.close()
