@@ -214,6 +214,26 @@ def obstacle_leg(p, steps, warmup, storages=("f32", "bf16"), solid_fraction=0.1)
     return out
 
 
+def inclined_leg(n, steps, warmup, storages=("f32", "bf16")):
+    """The miscible workload in the medium with annual rings inclined by 45
+    degrees in the x-y plane: K^-1 is a full symmetric tensor per cell, held
+    on the GPU as its eigenframe (unit quaternion) and eigenvalues, 7 planes.
+    Algorithmic bytes per cell: populations + porosity + 7 tensor values."""
+    from paper_0912_4230_amd import inputs as I
+    log(f"bench: generating the {n}^3 inclined-ring medium")
+    q = I.miscible(shape=(n, n, n), seed=0, ring_angle=45.0)
+    ncell = n ** 3
+    out = {"ring_angle_deg": 45.0, "tensor_planes": 7}
+    for st in storages:
+        ms, dg = time_gpu(q, st, steps, warmup)
+        s = ms / steps
+        bpl = storage_bpl(st) + 4 * 4     # 7 instead of 3 K^-1 values
+        out[st] = {"ms_per_step": round(s, 5), "MLUPS": round(ncell / s / 1e3, 1), "bytes_per_lup": bpl,
+                   "achieved_GBs": round(bpl * ncell / (s / 1e3) / 1e9, 1), "nonfinite": int(dg[7])}
+        log(f"bench: inclined rings {st}: {out[st]}")
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -244,6 +264,7 @@ def main():
     ap.add_argument("--no-reduced", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-obstacles", action="store_true")
+    ap.add_argument("--no-inclined", action="store_true")
     ap.add_argument("--precision", action="store_true",
                     help="also run the 512^3 precision form (FP32 / BF16 / FP16 storage, 2000 steps)")
     args = ap.parse_args()
@@ -312,6 +333,8 @@ def main():
         out["reduced_storage"] = red
     if not args.no_obstacles and args.storage == "f32":
         out["obstacles"] = obstacle_leg(p, min(args.steps, 300), args.warmup)
+    if not args.no_inclined and args.storage == "f32":
+        out["inclined_rings"] = inclined_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_serve:
         out["serving"] = serving_leg()
     if args.precision:
