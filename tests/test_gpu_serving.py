@@ -16,7 +16,9 @@ def _setup():
 
 
 def _stream():
-    reqs = I.request_stream(n=7, rate=40.0, edge_lo=18, edge_hi=40, steps_lo=30, steps_hi=140,
+    # arrivals within microseconds of each other: the requests are admitted
+    # together and overlap on the GPU however fast each one runs
+    reqs = I.request_stream(n=7, rate=1e6, edge_lo=18, edge_hi=40, steps_lo=30, steps_hi=140,
                             arrival_seed=11, param_seed=12, medium_seed0=500)
     # make sure both physics appear
     reqs[0].physics = I.IMMISCIBLE
