@@ -253,6 +253,33 @@ def cpu_baseline(budget_s=15.0):
             "sample": f"miscible physics, 64^3 crop of the seeded medium, {n} steps, FP64, {dt:.1f} s"}
 
 
+def cpu_baseline_full(threads_all):
+    """The CPU-baseline protocol in full: the FP64 oracle with one thread and
+    with all threads on the Poiseuille channel (32^3, 1000 steps, FP64 plain
+    method), and on the miscible and two-fluid physics at 64^3 x 200 steps.
+    MLUPS over all cells; a reported baseline, not a target."""
+    from oracle import oracle as O
+    from paper_0912_4230_amd import inputs as I
+    cases = [("poiseuille 32^3 x 1000 (plain method)", lambda: I.poiseuille(shape=(32, 32, 32)), 1000),
+             ("miscible 64^3 x 200", lambda: I.miscible(shape=(64, 64, 64), seed=0), 200),
+             ("two-fluid drop 64^3 x 200", lambda: I.drop(shape=(64, 64, 64), radius=10.0), 200)]
+    out = {"cores_all": threads_all}
+    for name, make, steps in cases:
+        row = {}
+        for nt in (1, threads_all):
+            O.set_threads(nt)
+            o = O.Oracle(make())
+            t0 = time.perf_counter()
+            o.step(steps)
+            dt = time.perf_counter() - t0
+            o.close()
+            row[f"threads_{nt}"] = {"MLUPS": round(o.n * steps / dt / 1e6, 2), "seconds": round(dt, 2)}
+            log(f"bench: cpu oracle {name}, {nt} threads: {dt:.1f} s")
+        out[name] = row
+    O.set_threads(threads_all)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +292,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--no-inclined", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle with 1 and all threads on the 32^3 channel and 64^3 x 200 steps")
     ap.add_argument("--precision", action="store_true",
                     help="also run the 512^3 precision form (FP32 / BF16 / FP16 storage, 2000 steps)")
     args = ap.parse_args()
@@ -342,6 +371,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()
+    if args.cpu_full:
+        out["cpu_baseline_full"] = cpu_baseline_full(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     print(json.dumps(out), flush=True)
 
 

@@ -53,6 +53,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 19
 
@@ -654,6 +657,17 @@ void orc_porous_velocity(const orc_params *p, double eps, const double kinv[3], 
                          const double V[3], double Vp[3], double Fext[3])
 {
     porous_velocity(p, eps, kinv, nu, V, Vp, Fext);
+}
+
+/* number of OpenMP threads of the following calls (the CPU baseline times
+ * the oracle with one thread and with all of them) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 /* full-tensor forms for the tests: K^-1/2 of one cell, and V', F^ext */

@@ -67,6 +67,7 @@ def lib():
         L.orc_porous_velocity.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
         L.orc_porous_velocity_full.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
         L.orc_sym_sqrt.argtypes = [dp, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -146,6 +147,11 @@ def porous_velocity(problem, eps, kinv, nu, V):
     fn = lib().orc_porous_velocity_full if k.size == 6 else lib().orc_porous_velocity
     fn(C.byref(prm), float(eps), _dp(k), float(nu), _dp(_vec(V)), _dp(Vp), _dp(Fx))
     return Vp, Fx
+
+
+def set_threads(n: int):
+    """OpenMP threads of the oracle's following calls from this thread."""
+    lib().orc_set_threads(int(n))
 
 
 def sym_sqrt(k6):
