@@ -129,3 +129,18 @@ def test_create_checks_before_gpu():
     assert L.lbm_moments(None, None, None, None, None) == B.LBM_EINVAL
     assert L.lbm_destroy(None) == B.LBM_EINVAL
     assert L.lbm_steps_done(None) == -1
+
+
+@pytest.mark.parametrize("storage,limit_cells", [(B.LBM_F64, 1 << 28), (B.LBM_F32, 1 << 29),
+                                                 (B.LBM_BF16_DEV, (1 << 30) - 64)])
+def test_maximum_lattice_sizes(storage, limit_cells):
+    """Planes are addressed by 32-bit byte offsets from a uniform base (a
+    bounce-back selects within a plane pair): the largest lattice of each
+    storage is accepted, one more z-plane is rejected.  No GPU call."""
+    nx = ny = 1024
+    nz = limit_cells // (nx * ny)
+    d = _desc(nx=nx, ny=ny, nz=nz, storage=storage)
+    ok = B.lbm_workspace_bytes(d)
+    assert ok > 2 * 19 * nx * ny * nz * {B.LBM_F64: 8, B.LBM_F32: 4}.get(storage, 2)
+    d = _desc(nx=nx, ny=ny, nz=nz + 1, storage=storage)
+    assert B.lbm_workspace_bytes(d) == 0
