@@ -33,17 +33,16 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 // Elements from one population plane to the next.  Every plane starts on a
 // 256-byte boundary (so that a wave's stores cover whole cache lines; with
-// planes at odd offsets two waves share the lines at every boundary), and
-// 16-bit planes are padded by a further 128 bytes: the 38 read and 38 write
-// streams of a step then do not all sit at the same offset modulo a
-// power-of-two plane size, which measured 4-7% faster on 16-bit storage and
-// no better on 4- and 8-byte.
+// planes at odd offsets two waves share the lines at every boundary) and is
+// followed by 512 bytes of padding: the 38 read and 38 write streams of a
+// step then do not all sit at the same offset modulo a power-of-two plane
+// size.  Measured against unpadded planes: FP32 256^3 -2%, 512^3 -7%; 16-bit
+// -4 to -7% (256, 768, 1024 and 2048 bytes measured no better).
 size_t plane_stride(const lbm_desc *d)
 {
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     const size_t sb = storage_bytes(d->storage), per = 256 / sb;
-    const size_t aligned = (n + per - 1) / per * per;
-    return sb == 2 ? aligned + 128 / 2 : aligned;
+    return (n + per - 1) / per * per + 512 / sb;
 }
 
 struct Layout {

@@ -131,14 +131,14 @@ def test_create_checks_before_gpu():
     assert L.lbm_steps_done(None) == -1
 
 
-@pytest.mark.parametrize("storage,limit_cells", [(B.LBM_F64, 1 << 28), (B.LBM_F32, 1 << 29),
-                                                 (B.LBM_BF16_DEV, (1 << 30) - 64)])
-def test_maximum_lattice_sizes(storage, limit_cells):
+@pytest.mark.parametrize("storage,nz", [(B.LBM_F64, 255), (B.LBM_F32, 511), (B.LBM_BF16_DEV, 1023)])
+def test_maximum_lattice_sizes(storage, nz):
     """Planes are addressed by 32-bit byte offsets from a uniform base (a
-    bounce-back selects within a plane pair): the largest lattice of each
-    storage is accepted, one more z-plane is rejected.  No GPU call."""
+    bounce-back selects within a plane pair of padded planes): with
+    1024 x 1024 planes, 255 / 511 / 1023 planes (FP64 / FP32 / 16-bit, just
+    under 2^28 / 2^29 / 2^30 cells) are accepted, one more is rejected.  No
+    GPU call."""
     nx = ny = 1024
-    nz = limit_cells // (nx * ny)
     d = _desc(nx=nx, ny=ny, nz=nz, storage=storage)
     ok = B.lbm_workspace_bytes(d)
     assert ok > 2 * 19 * nx * ny * nz * {B.LBM_F64: 8, B.LBM_F32: 4}.get(storage, 2)
