@@ -214,6 +214,19 @@ def obstacle_leg(p, steps, warmup, storages=("f32", "bf16"), solid_fraction=0.1)
     return out
 
 
+def plain_method_leg(steps=1000):
+    """The plain method at 32^3 in FP64: Poiseuille flow through a homogeneous
+    porous medium (eps 0.7, K 1e-2, G 1e-6, tau 0.8, walls at z = 0, 31), the
+    full 1000-step run timed on the device.  The lattice (10 MB of
+    populations) stays in the caches, so this is launch- and latency-bound:
+    MLUPS only, no roofline."""
+    from paper_0912_4230_amd import inputs as I
+    p = I.poiseuille(shape=(32, 32, 32))
+    ms, dg = time_gpu(p, "f64", steps, 20)
+    return {"grid": [32, 32, 32], "storage": "f64", "steps": steps, "ms_per_step": round(ms / steps, 5),
+            "MLUPS": round(32 ** 3 * steps / (ms / 1e3) / 1e6, 1), "max_v": dg[6], "nonfinite": int(dg[7])}
+
+
 def inclined_leg(n, steps, warmup, storages=("f32", "bf16")):
     """The miscible workload in the medium with annual rings inclined by 45
     degrees in the x-y plane: K^-1 is a full symmetric tensor per cell, held
@@ -362,6 +375,9 @@ def main():
         out["reduced_storage"] = red
     if not args.no_obstacles and args.storage == "f32":
         out["obstacles"] = obstacle_leg(p, min(args.steps, 300), args.warmup)
+    if args.storage == "f32":
+        out["plain_method_32"] = plain_method_leg()
+        log(f"bench: plain method 32^3 FP64: {out['plain_method_32']}")
     if not args.no_inclined and args.storage == "f32":
         out["inclined_rings"] = inclined_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_serve:
