@@ -42,6 +42,9 @@
  *  - two-fluid (immiscible) mode: second lattice g = fluid-1 populations,
  *    colour field rho_1 = Sum g, C = rho_1 / rho, nu = C nu_1 + (1-C) nu_2,
  *    recolouring g~_i = C f~_i + beta C (1-C) rho w_i cos(v_i, F);
+ *  - free-surface mode (Sec. 3): liquid, interface and gas cells, mass
+ *    exchange, reconstruction from gas cells and class conversion, with the
+ *    readings stated beside fs_step below;
  *  - walls: halfway bounce-back; reservoirs: cells held at the equilibrium
  *    of (rho_bc, V' = 0, C_bc); the cells of an optional obstacle mask are
  *    solid like wall cells, with their own contact angle.
@@ -59,7 +62,9 @@
 
 #define NQ 19
 
-enum { PHYS_SINGLE = 0, PHYS_MISCIBLE = 1, PHYS_IMMISCIBLE = 2 };
+enum { PHYS_SINGLE = 0, PHYS_MISCIBLE = 1, PHYS_IMMISCIBLE = 2, PHYS_FREESURF = 3 };
+/* free-surface cell classes (Sec. 3) */
+enum { FS_GAS = 0, FS_IF = 1, FS_LIQ = 2 };
 enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_RESERVOIR = 2 };
 enum { CELL_FLUID = 0, CELL_SOLID = 1, CELL_RESERVOIR = 2 };
 
@@ -131,6 +136,9 @@ typedef struct {
     double *rho, *vel, *conc; /* moments of the last step (pre-collision, Sec. 4) */
     double *vsnap;            /* V' at the previous diagnostic call */
     double *rho1;             /* colour field (immiscible) */
+    unsigned char *fst;       /* free surface: FS_GAS / FS_IF / FS_LIQ per non-solid cell */
+    double *mass, *lam;       /* free surface: liquid mass m and fill fraction lambda = m / rho */
+    double fs_lost;           /* free surface: excess mass without an interface neighbour */
     long step;                /* number of completed steps */
 } orc_state;
 
@@ -687,7 +695,279 @@ void orc_destroy(orc_state *s)
     free(s->eps); free(s->kinv); free(s->ksqrt); free(s->type); free(s->tface);
     free(s->f[0]); free(s->f[1]); free(s->h[0]); free(s->h[1]);
     free(s->rho); free(s->vel); free(s->conc); free(s->vsnap); free(s->rho1);
+    free(s->fst); free(s->mass); free(s->lam);
     free(s);
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Free-surface technique (Sec. 3; the method of the cited free-surface
+ * reference, whose details the paper defers to):  a liquid penetrating
+ * empty space.  Non-solid cells are liquid (full), gas (empty, no state) or
+ * interface (liquid mass m, fill fraction lambda = m / rho).
+ * Readings of the points the paper leaves open:
+ *  - mass exchange (Eq. deltamass) only over links to liquid or interface
+ *    neighbours: weight 1 to a liquid neighbour, (lambda(x) + lambda(y))/2 to
+ *    an interface neighbour, 0 to a gas cell (the printed average applied to
+ *    gas and liquid links would not conserve mass);
+ *  - populations arriving from a gas cell (Eq. equilempty) use the
+ *    equilibria at the gas density rho_A = 1 and the velocity of the
+ *    receiving cell's own post-collision populations (its state at t);
+ *  - conversion thresholds: m > (1 + kappa) rho -> liquid, m < -kappa rho ->
+ *    gas, kappa = 1e-3; a cell that would empty next to one that fills stays
+ *    interface; gas cells next to a new liquid cell become interface cells
+ *    with the equilibrium of the mean density and velocity of the
+ *    post-collision populations of their liquid / interface neighbours that
+ *    do not empty, and m = 0; liquid cells next to a new gas cell
+ *    become interface cells with m = rho;
+ *  - the excess mass of a converted cell (m - rho, or m for a new gas cell)
+ *    is shared equally among its neighbours that end the step as interface
+ *    cells (mass is lost only if there is none, and counted). */
+#define FS_KAPPA 1e-3
+#define FS_RHO_A 1.0
+enum { FS_NONE = 0, FS_TO_LIQ = 1, FS_TO_GAS = 2 };
+
+static int fs_open(const orc_state *s, long j)
+{
+    return j >= 0 && s->type[j] != CELL_SOLID;
+}
+
+/* set up the cell classes and masses from the initial fill fraction c0 */
+static int fs_init(orc_state *s, const double *c0, const double *rho0)
+{
+    long n = s->n;
+    s->fst = calloc(n, 1);
+    s->mass = calloc(n, sizeof(double));
+    s->lam = calloc(n, sizeof(double));
+    if (!s->fst || !s->mass || !s->lam) return -1;
+    for (long i = 0; i < n; ++i) {
+        if (s->type[i] != CELL_FLUID) continue;
+        double l = c0[i];
+        s->fst[i] = l >= 1.0 ? FS_LIQ : (l <= 0.0 ? FS_GAS : FS_IF);
+    }
+    /* a liquid cell next to a gas cell is an interface cell */
+    int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
+    unsigned char *t2 = malloc(n);
+    if (!t2) return -1;
+    memcpy(t2, s->fst, n);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                if (s->type[i] != CELL_FLUID || s->fst[i] != FS_LIQ) continue;
+                for (int q = 1; q < NQ; ++q) {
+                    long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                    if (fs_open(s, j) && s->fst[j] == FS_GAS) t2[i] = FS_IF;
+                }
+            }
+    memcpy(s->fst, t2, n);
+    free(t2);
+    for (long i = 0; i < n; ++i) {
+        if (s->type[i] != CELL_FLUID) continue;
+        double l = c0[i] < 0.0 ? 0.0 : (c0[i] > 1.0 ? 1.0 : c0[i]);
+        if (s->fst[i] == FS_GAS) {
+            for (int q = 0; q < NQ; ++q) s->f[0][(long)q * n + i] = 0.0;
+            s->rho[i] = 0.0;
+            for (int a = 0; a < 3; ++a) s->vel[a * n + i] = 0.0;
+            s->mass[i] = s->lam[i] = s->conc[i] = 0.0;
+        } else {
+            if (s->fst[i] == FS_LIQ) l = 1.0;
+            s->mass[i] = l * rho0[i];
+            s->lam[i] = l;
+            s->conc[i] = l;
+        }
+    }
+    return 0;
+}
+
+/* One free-surface step: stream the populations and the mass, collide,
+ * then redefine the cell classes (flowchart of Sec. 4).                    */
+static int fs_step(orc_state *s, double t)
+{
+    const orc_params *p = &s->p;
+    long n = s->n;
+    int nx = p->nx, ny = p->ny, nz = p->nz;
+    const double *Fc = s->f[s->cur];
+    double *Fn = s->f[1 - s->cur];
+    double *mnew = malloc(sizeof(double) * n), *share = calloc(n, sizeof(double));
+    unsigned char *flag = calloc(n, 1), *flag2 = calloc(n, 1), *nt = malloc(n);
+    if (!mnew || !share || !flag || !flag2 || !nt) {
+        free(mnew); free(share); free(flag); free(flag2); free(nt);
+        return -1;
+    }
+
+    /* 1. stream (with the gas-side reconstruction), exchange mass, collide */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                mnew[i] = 0.0;
+                if (s->type[i] != CELL_FLUID) continue;
+                if (s->fst[i] == FS_GAS) {
+                    for (int q = 0; q < NQ; ++q) Fn[(long)q * n + i] = 0.0;
+                    continue;
+                }
+                double own[NQ], fin[NQ], hin[NQ], fo[NQ], ho[NQ], mom[5];
+                double orho = 1.0, oj[3] = {0.0, 0.0, 0.0};
+                for (int q = 0; q < NQ; ++q) {
+                    own[q] = Fc[(long)q * n + i];
+                    orho += own[q];
+                    for (int a = 0; a < 3; ++a) oj[a] += own[q] * VEL[q][a];
+                    hin[q] = 0.0;
+                }
+                double ou[3] = {oj[0] / orho, oj[1] / orho, oj[2] / orho};
+                double eqA[NQ], F0[3] = {0.0, 0.0, 0.0};
+                feq_dev(FS_RHO_A - 1.0, ou, s->eps[i], 1.0, 0.0, F0, eqA);
+                for (int q = 0; q < NQ; ++q) {
+                    long j = neighbour(s, x, y, z, -VEL[q][0], -VEL[q][1], -VEL[q][2]);
+                    if (!fs_open(s, j)) fin[q] = own[OPP[q]];
+                    else if (s->fst[j] == FS_GAS) fin[q] = eqA[q] + eqA[OPP[q]] - own[OPP[q]];
+                    else fin[q] = Fc[(long)q * n + j];
+                }
+                double m = s->mass[i];
+                if (s->fst[i] == FS_IF) {
+                    double dm = 0.0;
+                    for (int q = 1; q < NQ; ++q) {
+                        long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                        if (!fs_open(s, j) || s->fst[j] == FS_GAS) continue;
+                        double flux = Fc[(long)OPP[q] * n + j] - own[q];
+                        dm += s->fst[j] == FS_LIQ ? flux : flux * 0.5 * (s->lam[i] + s->lam[j]);
+                    }
+                    m += dm;
+                }
+                collide_cell(s, x, y, z, t, fin, hin, fo, ho, mom);
+                for (int q = 0; q < NQ; ++q) Fn[(long)q * n + i] = fo[q];
+                double rho = mom[0];
+                if (s->fst[i] == FS_LIQ) m = rho;
+                mnew[i] = m;
+                s->rho[i] = rho;
+                for (int a = 0; a < 3; ++a) s->vel[a * n + i] = mom[1 + a];
+                if (s->fst[i] == FS_IF) {
+                    if (m > (1.0 + FS_KAPPA) * rho) flag[i] = FS_TO_LIQ;
+                    else if (m < -FS_KAPPA * rho) flag[i] = FS_TO_GAS;
+                }
+            }
+
+    /* 2. conflicts and the new classes */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                nt[i] = s->type[i] == CELL_FLUID ? s->fst[i] : FS_GAS;
+                flag2[i] = flag[i];
+                if (s->type[i] != CELL_FLUID) continue;
+                int near_liq = 0;
+                for (int q = 1; q < NQ; ++q) {
+                    long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                    if (fs_open(s, j) && flag[j] == FS_TO_LIQ) near_liq = 1;
+                }
+                if (flag[i] == FS_TO_GAS && near_liq) flag2[i] = FS_NONE;
+                if (s->fst[i] == FS_GAS && near_liq) nt[i] = FS_IF;
+            }
+    /* converting cells take their new class; a liquid cell next to a cell
+     * that empties after all becomes an interface cell */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                if (s->type[i] != CELL_FLUID) continue;
+                if (flag2[i] == FS_TO_LIQ) nt[i] = FS_LIQ;
+                else if (flag2[i] == FS_TO_GAS) nt[i] = FS_GAS;
+                else if (s->fst[i] == FS_LIQ) {
+                    int near_gas = 0;
+                    for (int q = 1; q < NQ; ++q) {
+                        long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                        if (fs_open(s, j) && flag2[j] == FS_TO_GAS) near_gas = 1;
+                    }
+                    nt[i] = near_gas ? FS_IF : FS_LIQ;
+                }
+            }
+
+    /* 3. gas cells turned interface: equilibrium of the mean density and
+     *    velocity of the post-collision populations of their liquid and
+     *    interface neighbours (the neighbours' state at the end of the step) */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                if (s->type[i] != CELL_FLUID || s->fst[i] != FS_GAS || nt[i] != FS_IF) continue;
+                double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
+                int k = 0;
+                for (int q = 1; q < NQ; ++q) {
+                    long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                    if (!fs_open(s, j) || s->fst[j] == FS_GAS || flag2[j] == FS_TO_GAS) continue;
+                    double r = 1.0, jm[3] = {0.0, 0.0, 0.0};
+                    for (int r2 = 0; r2 < NQ; ++r2) {
+                        double v = Fn[(long)r2 * n + j];
+                        r += v;
+                        for (int a = 0; a < 3; ++a) jm[a] += v * VEL[r2][a];
+                    }
+                    rs += r;
+                    for (int a = 0; a < 3; ++a) us[a] += jm[a] / r;
+                    ++k;
+                }
+                double ra = rs / k, ua[3] = {us[0] / k, us[1] / k, us[2] / k}, fo[NQ], F0[3] = {0.0, 0.0, 0.0};
+                double tau = 0.5 + 3.0 * viscosity(p, 0.0, t);
+                feq_dev(ra - 1.0, ua, s->eps[i], tau, 0.0, F0, fo);
+                for (int q = 0; q < NQ; ++q) Fn[(long)q * n + i] = fo[q];
+                s->rho[i] = ra;
+                for (int a = 0; a < 3; ++a) s->vel[a * n + i] = ua[a];
+                mnew[i] = 0.0;
+            }
+
+    /* 4. excess mass of the converted cells, shared among the neighbours that
+     *    end the step as interface cells */
+    double lost = 0.0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                if (s->type[i] != CELL_FLUID || flag2[i] == FS_NONE) continue;
+                double ex = flag2[i] == FS_TO_LIQ ? mnew[i] - s->rho[i] : mnew[i];
+                int k = 0;
+                for (int q = 1; q < NQ; ++q) {
+                    long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                    if (fs_open(s, j) && nt[j] == FS_IF && flag2[j] == FS_NONE) ++k;
+                }
+                share[i] = k > 0 ? ex / k : 0.0;
+                if (k == 0) lost += ex;
+            }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long i = cidx(s, x, y, z);
+                if (s->type[i] != CELL_FLUID) continue;
+                double m = mnew[i];
+                if (nt[i] == FS_IF) {
+                    for (int q = 1; q < NQ; ++q) {
+                        long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+                        if (fs_open(s, j) && flag2[j] != FS_NONE) m += share[j];
+                    }
+                } else if (nt[i] == FS_LIQ) {
+                    m = s->rho[i];
+                } else {
+                    m = 0.0;
+                }
+                s->mass[i] = m;
+            }
+    /* 5. new classes, fill fractions, moments of gas cells */
+    for (long i = 0; i < n; ++i) {
+        if (s->type[i] != CELL_FLUID) continue;
+        s->fst[i] = nt[i];
+        if (nt[i] == FS_GAS) {
+            s->lam[i] = 0.0;
+            s->rho[i] = 0.0;
+            for (int a = 0; a < 3; ++a) s->vel[a * n + i] = 0.0;
+            for (int q = 0; q < NQ; ++q) Fn[(long)q * n + i] = 0.0;
+        } else {
+            s->lam[i] = nt[i] == FS_LIQ ? 1.0 : s->mass[i] / s->rho[i];
+        }
+        s->conc[i] = s->lam[i];
+    }
+    s->fs_lost += lost;
+    free(mnew); free(share); free(flag); free(flag2); free(nt);
+    return 0;
 }
 
 /* Create the state and apply the initial conditions (flowchart, first three
@@ -701,6 +981,9 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
                       const unsigned char *solid)
 {
     lattice_setup();
+    if (p->physics == PHYS_FREESURF)
+        for (int f = 0; f < 6; ++f)
+            if (p->face_kind[f] == FACE_RESERVOIR) return NULL;
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     if (!s) return NULL;
     s->p = *p;
@@ -782,6 +1065,7 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
                     s->h[0][(long)q * n + i] = ho[q];
                 }
             }
+    if (p->physics == PHYS_FREESURF && fs_init(s, c0, rho0) != 0) { orc_destroy(s); return NULL; }
     memcpy(s->vsnap, s->vel, sizeof(double) * 3 * n);
     s->step = 0;
     return s;
@@ -802,6 +1086,12 @@ int orc_step(orc_state *s, int nsteps)
     int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
     for (int it = 0; it < nsteps; ++it) {
         double t = (double)(s->step + 1);
+        if (s->p.physics == PHYS_FREESURF) {
+            if (fs_step(s, t) != 0) return -1;
+            s->cur = 1 - s->cur;
+            s->step += 1;
+            continue;
+        }
         const double *Fc = s->f[s->cur], *Hc = s->h[s->cur];
         double *Fn = s->f[1 - s->cur], *Hn = s->h[1 - s->cur];
         if (s->p.physics == PHYS_IMMISCIBLE) colour_field(s, 1);
@@ -849,8 +1139,9 @@ void orc_moments(const orc_state *s, double *rho, double *vel, double *conc)
     if (conc) memcpy(conc, s->conc, sizeof(double) * n);
 }
 
-/* Diagnostics over fluid cells: {Sum rho, Sum rho V'_x, _y, _z, Sum eps C
- * (miscible) or Sum rho_1 (two-fluid) or 0, |V' - V'_snap|^2 / |V'|^2,
+/* Diagnostics over fluid cells (free surface: liquid and interface cells):
+ * {Sum rho, Sum rho V'_x, _y, _z, Sum eps C (miscible) or Sum rho_1
+ * (two-fluid) or Sum m (free surface) or 0, |V' - V'_snap|^2 / |V'|^2,
  * max |V'|, number of cells with a non-finite moment}.  The snapshot is
  * replaced by the current V'.                                              */
 void orc_diag(orc_state *s, double out[8])
@@ -859,12 +1150,14 @@ void orc_diag(orc_state *s, double out[8])
     double acc[7] = {0, 0, 0, 0, 0, 0, 0}, vmax = 0.0, bad = 0.0;
     for (long i = 0; i < n; ++i) {
         if (s->type[i] != CELL_FLUID) continue;
+        if (s->p.physics == PHYS_FREESURF && s->fst[i] == FS_GAS) continue;
         double r = s->rho[i], u[3] = {s->vel[i], s->vel[n + i], s->vel[2 * n + i]}, c = s->conc[i];
         if (!isfinite(r) || !isfinite(u[0]) || !isfinite(u[1]) || !isfinite(u[2]) || !isfinite(c)) { bad += 1.0; continue; }
         acc[0] += r;
         for (int a = 0; a < 3; ++a) acc[1 + a] += r * u[a];
         if (s->p.physics == PHYS_MISCIBLE) acc[4] += s->eps[i] * c;
         else if (s->p.physics == PHYS_IMMISCIBLE) acc[4] += c * r;
+        else if (s->p.physics == PHYS_FREESURF) acc[4] += s->mass[i];
         double du = 0.0, uu = 0.0;
         for (int a = 0; a < 3; ++a) {
             double d = u[a] - s->vsnap[a * n + i];
@@ -904,6 +1197,7 @@ void orc_set_state(orc_state *s, int L, const double *in, long step)
 void orc_step_cells(orc_state *s, long ncells, const long *cells, double *fo_out,
                     double *ho_out, double *mom_out)
 {
+    if (s->p.physics == PHYS_FREESURF) return;   /* the class update is not local */
     double t = (double)(s->step + 1);
     const double *Fc = s->f[s->cur], *Hc = s->h[s->cur];
     if (s->p.physics == PHYS_IMMISCIBLE) colour_field(s, 1);
@@ -934,3 +1228,16 @@ void orc_step_cells(orc_state *s, long ncells, const long *cells, double *fo_out
 
 /* cell classes (0 fluid, 1 solid, 2 reservoir) */
 void orc_cell_types(const orc_state *s, unsigned char *out) { memcpy(out, s->type, s->n); }
+
+/* free surface: per cell class (0 gas, 1 interface, 2 liquid; solid cells 0)
+ * and liquid mass m; the total excess mass that found no interface cell to
+ * take it.  Returns -1 for the other physics.                             */
+double orc_fs_state(const orc_state *s, unsigned char *cls, double *mass)
+{
+    if (s->p.physics != PHYS_FREESURF) return -1.0;
+    for (long i = 0; i < s->n; ++i) {
+        if (cls) cls[i] = s->type[i] == CELL_FLUID ? s->fst[i] : FS_GAS;
+        if (mass) mass[i] = s->type[i] == CELL_FLUID ? s->mass[i] : 0.0;
+    }
+    return s->fs_lost;
+}

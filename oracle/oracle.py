@@ -68,6 +68,8 @@ def lib():
         L.orc_porous_velocity_full.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
         L.orc_sym_sqrt.argtypes = [dp, dp]
         L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_fs_state.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte), dp]
+        L.orc_fs_state.restype = C.c_double
         _lib = L
     return _lib
 
@@ -179,7 +181,7 @@ class Oracle:
         sp = solid.ctypes.data_as(C.POINTER(C.c_ubyte)) if solid is not None else None
         h = lib().orc_create(C.byref(self.params), *[_dp(a) for a in self._keep], sp)
         if not h:
-            raise MemoryError("oracle allocation failed")
+            raise MemoryError("oracle allocation failed (or a reservoir face with the free surface)")
         self.h = C.c_void_p(h)
         self._keep = None
 
@@ -222,6 +224,16 @@ class Oracle:
         out = (C.c_ubyte * self.n)()
         lib().orc_cell_types(self.h, out)
         return np.frombuffer(out, dtype=np.uint8).copy().reshape(nz, ny, nx)
+
+    def fs_state(self):
+        """Free surface: (cell class (nz,ny,nx) 0 gas / 1 interface / 2 liquid,
+        liquid mass m (nz,ny,nx), excess mass lost so far)."""
+        nx, ny, nz = self.shape
+        cls = (C.c_ubyte * self.n)()
+        m = np.zeros(self.n)
+        lost = lib().orc_fs_state(self.h, cls, _dp(m))
+        return (np.frombuffer(cls, dtype=np.uint8).copy().reshape(nz, ny, nx),
+                m.reshape(nz, ny, nx), lost)
 
     def get_state(self, lattice_id: int):
         out = np.zeros(NQ * self.n)

@@ -21,8 +21,9 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 PERIODIC, WALL, RESERVOIR = 0, 1, 2
-SINGLE, MISCIBLE, IMMISCIBLE = 0, 1, 2
-PHYSICS_NAMES = {"single": SINGLE, "miscible": MISCIBLE, "immiscible": IMMISCIBLE}
+SINGLE, MISCIBLE, IMMISCIBLE, FREESURF = 0, 1, 2, 3
+PHYSICS_NAMES = {"single": SINGLE, "miscible": MISCIBLE, "immiscible": IMMISCIBLE,
+                 "freesurface": FREESURF}
 
 
 @dataclasses.dataclass
@@ -60,7 +61,7 @@ class Problem:
     kinv: Optional[np.ndarray] = None   # (3,nz,ny,nx) diagonal, or (6,nz,ny,nx) full {xx,yy,zz,xy,xz,yz}
     rho0: Optional[np.ndarray] = None   # (nz,ny,nx)
     vel0: Optional[np.ndarray] = None   # (3,nz,ny,nx)
-    c0: Optional[np.ndarray] = None     # (nz,ny,nx)
+    c0: Optional[np.ndarray] = None     # (nz,ny,nx); free surface: initial fill fraction
     solid: Optional[np.ndarray] = None  # (nz,ny,nx) nonzero = obstacle cell (no state, bounce-back)
     solid_angle: float = 90.0           # contact angle of the obstacle surfaces (two-fluid model)
 
@@ -275,6 +276,72 @@ def drop(shape=(128, 128, 128), radius=20.0, centre=None, speed=0.05, tau1=0.7, 
         faces[5] = Face(kind=WALL, angle=top_angle)
     p = Problem(shape=tuple(shape), physics=IMMISCIBLE, tau1=tau1, tau2=tau2, A=A, beta=beta,
                 faces=faces, c0=c0, vel0=vel0)
+    return p.fill_defaults()
+
+
+def falling_drop(shape=(140, 140, 1), radius=8.0, centre=None, G=1e-6, tau=0.7, axis=1,
+                 wall=True, speed=0.0) -> Problem:
+    """Free-surface drop falling onto an impermeable plane (Sec. 5.3): a liquid
+    disc (quasi-2D when the third extent is 1) or sphere of the given radius
+    in gas, gravity G toward -axis, a wall on the low face of that axis,
+    every other face periodic; no porous medium (eps = 1, K^-1 = 0).  The
+    fill fraction of a cell is its covered volume estimated on a 4^3
+    subgrid, so the drop's initial liquid mass is close to pi R^2 (or
+    4 pi R^3 / 3) for any centre."""
+    nx, ny, nz = shape
+    if centre is None:
+        centre = [nx / 2.0, ny / 2.0, nz / 2.0]
+        centre[axis] = shape[axis] / 2.0
+        if shape[2] == 1:
+            centre[2] = 0.0
+    sub = (np.arange(4) + 0.5) / 4.0 - 0.5
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    frac = np.zeros((nz, ny, nx))
+    flat = shape[2] == 1
+    for a in sub:
+        for b in sub:
+            for c in ([0.0] if flat else sub):
+                d2 = (x + a - centre[0]) ** 2 + (y + b - centre[1]) ** 2
+                if not flat:
+                    d2 = d2 + (z + c - centre[2]) ** 2
+                frac += d2 <= radius * radius
+    frac /= 16.0 if flat else 64.0
+    g = [0.0, 0.0, 0.0]
+    g[axis] = -G
+    vel0 = np.zeros((3, nz, ny, nx))
+    vel0[axis][frac > 0] = -speed
+    faces = [Face() for _ in range(6)]
+    if wall:
+        faces[2 * axis] = Face(kind=WALL)
+    p = Problem(shape=tuple(shape), physics=FREESURF, G=tuple(g), nu0=(tau - 0.5) / 3.0,
+                faces=faces, c0=frac, vel0=vel0)
+    return p.fill_defaults()
+
+
+def pool(shape=(6, 5, 40), depth=20.5, G=1e-4, tau=0.8) -> Problem:
+    """Free-surface liquid pool at rest: liquid up to the height `depth`
+    (the cell straddling it partly filled) above a wall at z = 0, gas above,
+    gravity G toward -z, periodic in x and y."""
+    nx, ny, nz = shape
+    zc = np.arange(nz, dtype=np.float64)[:, None, None] * np.ones((nz, ny, nx))
+    # the wall cell z = 0 is solid; liquid fills from its face z = 0.5 upward
+    c0 = np.clip(depth - (zc - 0.5), 0.0, 1.0)
+    faces = [Face() for _ in range(6)]
+    faces[4] = Face(kind=WALL)
+    p = Problem(shape=tuple(shape), physics=FREESURF, G=(0.0, 0.0, -G), nu0=(tau - 0.5) / 3.0,
+                faces=faces, c0=c0)
+    return p.fill_defaults()
+
+
+def slab(shape=(48, 4, 3), lo=8, hi=20, speed=0.05, tau=0.8) -> Problem:
+    """Free-surface liquid slab lo <= x < hi moving with velocity `speed`
+    along x through gas, periodic on every face, no force."""
+    nx, ny, nz = shape
+    x = np.arange(nx)[None, None, :] * np.ones((nz, ny, nx))
+    c0 = ((x >= lo) & (x < hi)).astype(np.float64)
+    vel0 = np.zeros((3, nz, ny, nx))
+    vel0[0] = speed
+    p = Problem(shape=tuple(shape), physics=FREESURF, nu0=(tau - 0.5) / 3.0, c0=c0, vel0=vel0)
     return p.fill_defaults()
 
 
