@@ -716,9 +716,9 @@ void orc_destroy(orc_state *s)
  *  - conversion thresholds: m > (1 + kappa) rho -> liquid, m < -kappa rho ->
  *    gas, kappa = 1e-3; a cell that would empty next to one that fills stays
  *    interface; gas cells next to a new liquid cell become interface cells
- *    with the equilibrium of the mean density and velocity of the
- *    post-collision populations of their liquid / interface neighbours that
- *    do not empty, and m = 0; liquid cells next to a new gas cell
+ *    with the equilibrium of the mean density and velocity (rho and V' of
+ *    the step) of their liquid / interface neighbours that do not empty, and
+ *    m = 0; liquid cells next to a new gas cell
  *    become interface cells with m = rho;
  *  - the excess mass of a converted cell (m - rho, or m for a new gas cell)
  *    is shared equally among its neighbours that end the step as interface
@@ -885,8 +885,8 @@ static int fs_step(orc_state *s, double t)
             }
 
     /* 3. gas cells turned interface: equilibrium of the mean density and
-     *    velocity of the post-collision populations of their liquid and
-     *    interface neighbours (the neighbours' state at the end of the step) */
+     *    velocity (rho and V' of this step) of their liquid and interface
+     *    neighbours that do not empty */
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -897,14 +897,8 @@ static int fs_step(orc_state *s, double t)
                 for (int q = 1; q < NQ; ++q) {
                     long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
                     if (!fs_open(s, j) || s->fst[j] == FS_GAS || flag2[j] == FS_TO_GAS) continue;
-                    double r = 1.0, jm[3] = {0.0, 0.0, 0.0};
-                    for (int r2 = 0; r2 < NQ; ++r2) {
-                        double v = Fn[(long)r2 * n + j];
-                        r += v;
-                        for (int a = 0; a < 3; ++a) jm[a] += v * VEL[r2][a];
-                    }
-                    rs += r;
-                    for (int a = 0; a < 3; ++a) us[a] += jm[a] / r;
+                    rs += s->rho[j];
+                    for (int a = 0; a < 3; ++a) us[a] += s->vel[a * n + j];
                     ++k;
                 }
                 double ra = rs / k, ua[3] = {us[0] / k, us[1] / k, us[2] / k}, fo[NQ], F0[3] = {0.0, 0.0, 0.0};
