@@ -247,6 +247,74 @@ def inclined_leg(n, steps, warmup, storages=("f32", "bf16")):
     return out
 
 
+def fs_bytes_per_live_cell(st):
+    """Algorithmic bytes of the free-surface stream/collide launch per liquid or
+    interface cell: one lattice read and written + porosity + 3 K^-1 values."""
+    sb = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "bf16s": 2, "f16s": 2}[st]
+    rb = 8 if st == "f64" else 4
+    return 2 * 19 * sb + 4 * rb + (2 * 4 if st in ("bf16s", "f16s") else 0)
+
+
+def freesurface_leg(n, steps, warmup, storages=("f32", "bf16")):
+    """Free surface (Sec. 3).  (a) Liquid penetrating the unsaturated
+    spruce-like medium, n^3, liquid in the upper half, gravity along the
+    grain: five launches per step; algorithmic bytes of the step = the
+    stream/collide of the live cells (fs_bytes_per_live_cell) + 2 bytes per
+    cell (class read, flag written) + 9 bytes per cell for the class passes.
+    (b) The paper's droplet (Sec. 5.3): 140x140x1, R = 8, tau = 0.7, G = 1e-6,
+    20000 steps in FP64, timed whole; total-mass error."""
+    import torch
+    from paper_0912_4230_amd import inputs as I
+    from paper_0912_4230_amd.sim import Simulation
+    log(f"bench: generating the {n}^3 penetration problem")
+    q = I.penetration(shape=(n, n, n), seed=0)
+    ncell = n ** 3
+    out = {"workload": f"penetration {n}^3: spruce-like medium 100:1:1 (K_ref 1), liquid y >= n/2, G 1e-4 along -y"}
+    for st in storages:
+        sim = Simulation(q, storage=st, diag_every=100)
+        M0 = sim.diag()[4]
+        sim.step(warmup)
+        live = int((sim.free_surface()[0] <= 2).logical_and(sim.free_surface()[0] >= 1).sum().item())
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(sim.stream)
+        sim.step(steps)
+        t1.record(sim.stream)
+        torch.cuda.synchronize()
+        s = t0.elapsed_time(t1) / steps
+        dg = sim.diag(check=False)
+        cls = sim.free_surface()[0]
+        nif = int((cls == 1).sum().item())
+        b = fs_bytes_per_live_cell(st) * live + 11 * ncell
+        out[st] = {"ms_per_step": round(s, 5), "MLUPS_all_cells": round(ncell / s / 1e3, 1),
+                   "MLUPS_live_cells": round(live / s / 1e3, 1), "live_cells": live, "interface_cells": nif,
+                   "achieved_GBs_step": round(b / (s / 1e3) / 1e9, 1),
+                   "mass_drift": float(dg[4] / M0 - 1.0), "nonfinite": int(dg[7])}
+        log(f"bench: free surface {st}: {out[st]}")
+        sim.close()
+        torch.cuda.empty_cache()
+    G, R = 1e-6, 8.0
+    p = I.falling_drop(shape=(140, 140, 1), radius=R, centre=(70.0, 0.5 + R + 0.5 * G * 10600.0 ** 2, 0.0), G=G,
+                       tau=0.7)
+    sim = Simulation(p, storage="f64", diag_every=1000)
+    M0 = sim.diag()[4]
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(sim.stream)
+    sim.step(20000)
+    t1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    dg = sim.diag(check=False)
+    out["paper_droplet"] = {"grid": [140, 140, 1], "steps": 20000, "storage": "f64", "total_ms": round(ms, 1),
+                            "us_per_step": round(1e3 * ms / 20000, 2), "mass_error": float(abs(dg[4] / M0 - 1.0))}
+    log(f"bench: paper droplet: {out['paper_droplet']}")
+    sim.close()
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -305,6 +373,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--no-inclined", action="store_true")
+    ap.add_argument("--no-freesurface", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle with 1 and all threads on the 32^3 channel and 64^3 x 200 steps")
     ap.add_argument("--precision", action="store_true",
@@ -380,6 +449,8 @@ def main():
         log(f"bench: plain method 32^3 FP64: {out['plain_method_32']}")
     if not args.no_inclined and args.storage == "f32":
         out["inclined_rings"] = inclined_leg(n, min(args.steps, 300), args.warmup)
+    if not args.no_freesurface and args.storage == "f32":
+        out["free_surface"] = freesurface_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_serve:
         out["serving"] = serving_leg()
     if args.precision:

@@ -18,7 +18,12 @@
  *   - walls (halfway bounce-back, with a wall colour that sets the contact
  *     angle in two-fluid mode), fixed-state reservoirs (pressure inlet /
  *     outlet) and periodic faces (Sec. 4, boundary conditions), and optional
- *     obstacle cells anywhere in the box given by a per-cell mask.
+ *     obstacle cells anywhere in the box given by a per-cell mask;
+ *   - or, instead of the second lattice, the free-surface technique of
+ *     Sec. 3 (liquid penetrating empty space): liquid, interface and gas
+ *     cells, the liquid mass of interface cells (Eqs. massmacro, massevol,
+ *     deltamass), populations rebuilt on links from gas cells (Eq.
+ *     equilempty) and the conversion of cells as they fill and empty.
  *
  * One time step follows the simulation procedure of Sec. 4 (flowchart):
  * stream both lattices, take the moments, form the colour gradient, collide.
@@ -62,8 +67,41 @@ typedef enum {
 typedef enum {
     LBM_SINGLE = 0,      /* hydrodynamic lattice only */
     LBM_MISCIBLE = 1,    /* + solute lattice (Sec. 2.2) */
-    LBM_IMMISCIBLE = 2   /* + fluid-1 lattice of a two-fluid colour model */
+    LBM_IMMISCIBLE = 2,  /* + fluid-1 lattice of a two-fluid colour model */
+    LBM_FREESURF = 3     /* hydrodynamic lattice + free surface (Sec. 3) */
 } lbm_physics;
+/* Free surface (LBM_FREESURF).  Every non-solid cell is liquid, interface
+ * or gas.  Gas cells carry no state.  Liquid and interface cells stream and
+ * collide like the single-fluid model (porous medium, force and viscosity
+ * law included).  Each step:
+ *  1. an interface cell x exchanges liquid mass with every liquid or
+ *     interface neighbour y = x + v_i: dm_i = w (f~_opp(i)(y) - f~_i(x)),
+ *     with w = 1 for a liquid y and (lambda(x) + lambda(y)) / 2 for an
+ *     interface y (Eq. deltamass; weight 1 on liquid links is what conserves
+ *     mass);
+ *  2. a population that would stream in from a gas cell is
+ *     f_i = f^eq_i + f^eq_opp(i) - f~_opp(i)(x), the equilibria taken at the
+ *     gas density 1 and the velocity of x's own post-collision populations
+ *     (Eq. equilempty);
+ *  3. after the collision, an interface cell with m > (1 + 1e-3) rho fills
+ *     (becomes liquid) and one with m < -1e-3 rho empties (becomes gas),
+ *     unless it touches a filling cell; gas cells next to a filling cell
+ *     become interface cells with the equilibrium of the mean density and
+ *     velocity (rho and V' of the step) of their liquid and interface
+ *     neighbours that do not empty, and m = 0; liquid cells
+ *     next to an emptying cell become interface cells with m = rho;
+ *  4. the excess m - rho of a filled cell, or m of an emptied one, is shared
+ *     equally among its neighbours that are interface cells after the step
+ *     and did not convert (if there is none, it is lost and counted).
+ * Then lambda = m / rho (1 for liquid, 0 for gas).  lbm_medium.c0 holds the
+ * initial fill fraction: >= 1 liquid, <= 0 gas, else an interface cell with
+ * m = c0 rho0; a liquid cell next to a gas cell starts as an interface cell
+ * with m = rho0.  Reservoir faces are rejected.  lbm_moments reports lambda
+ * as the concentration; rho and V' of gas cells read 0; the diagnostics run
+ * over liquid and interface cells, with diag[4] = the total liquid mass
+ * (Sum of m over interface cells + Sum of rho over liquid cells).  The
+ * conversion decisions are taken in double precision on masses kept in
+ * double precision in every storage mode. */
 
 typedef enum {
     LBM_F64 = 0,         /* populations and fields in double */
@@ -138,7 +176,8 @@ typedef struct {
                                    K^-1); NULL: kinv_uniform (diagonal) */
     const void *rho0;           /* ncell initial densities > 0; NULL: 1 */
     const void *vel0;           /* 3 planes, initial velocity V' ; NULL: 0 */
-    const void *c0;             /* ncell initial concentrations; NULL: 0 */
+    const void *c0;             /* ncell initial concentrations (free surface: initial
+                                   fill fractions); NULL: 0 */
     double eps_uniform;
     double kinv_uniform[3];
     const unsigned char *solid; /* ncell bytes, nonzero = obstacle cell; only with
@@ -204,6 +243,15 @@ lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8
  * deviations f_i - w_i) or 1 (second lattice, as is), decoded to the real
  * type: 19 planes in the direction order of lbm_lattice(). */
 lbm_status lbm_populations(lbm_t h, int lattice, void *dst);
+
+/* Free surface (Sec. 3): the cell classes after the last step (ncell bytes:
+ * 0 gas, 1 interface, 2 liquid, 3 solid) and the liquid mass per cell
+ * (ncell doubles: m for interface cells, rho for liquid cells, 0 for gas and
+ * solid), into caller device buffers (each may be NULL), and into *lost (host,
+ * may be NULL) the excess mass that found no interface cell to take it since
+ * lbm_set_medium.  LBM_EINVAL for a handle of another physics.  Synchronises
+ * the stream. */
+lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lost);
 
 /* Completed steps since lbm_set_medium, or -1 for a NULL handle. */
 long long lbm_steps_done(lbm_t h);

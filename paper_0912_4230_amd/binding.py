@@ -13,15 +13,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libporolbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = range(6)
-LBM_SINGLE, LBM_MISCIBLE, LBM_IMMISCIBLE = range(3)
+LBM_SINGLE, LBM_MISCIBLE, LBM_IMMISCIBLE, LBM_FREESURF = range(4)
 LBM_F64, LBM_F32, LBM_BF16_DEV, LBM_F16_DEV, LBM_BF16_SPLIT, LBM_F16_SPLIT = range(6)
 LBM_FACE_PERIODIC, LBM_FACE_WALL, LBM_FACE_RESERVOIR = range(3)
 
 STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV,
                  "bf16s": LBM_BF16_SPLIT, "f16s": LBM_F16_SPLIT}
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_medium", "lbm_step", "lbm_step_batch",
-            "lbm_moments", "lbm_populations", "lbm_steps_done", "lbm_destroy", "lbm_lattice",
-            "lbm_strerror"]
+            "lbm_moments", "lbm_populations", "lbm_free_surface", "lbm_steps_done", "lbm_destroy",
+            "lbm_lattice", "lbm_strerror"]
 
 
 class lbm_face(C.Structure):
@@ -90,6 +90,8 @@ def lib():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_lattice.restype = None
         L.lbm_lattice.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.lbm_free_surface.restype = C.c_int
+        L.lbm_free_surface.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_strerror.argtypes = [C.c_int]
         _lib = L
@@ -140,6 +142,15 @@ def lbm_moments(h, rho_ptr: int = 0, vel_ptr: int = 0, conc_ptr: int = 0, diag=N
 
 def lbm_populations(h, lattice: int, dst_ptr: int) -> int:
     return _check(lib().lbm_populations(h, int(lattice), C.c_void_p(dst_ptr)), "lbm_populations")
+
+
+def lbm_free_surface(h, cls_ptr: int = 0, mass_ptr: int = 0) -> float:
+    """Free surface: classes (uint8) and masses (double) into device buffers
+    (0: skip); returns the lost excess mass."""
+    lost = C.c_double(0.0)
+    _check(lib().lbm_free_surface(h, C.c_void_p(cls_ptr or None), C.c_void_p(mass_ptr or None), C.byref(lost)),
+           "lbm_free_surface")
+    return float(lost.value)
 
 
 def lbm_steps_done(h) -> int:

@@ -1,0 +1,619 @@
+// freesurf.hpp -- the free-surface technique of Sec. 3 on gfx950: liquid,
+// interface and gas cells, the liquid mass of interface cells (Eqs.
+// massmacro, massevol, deltamass), populations rebuilt on links from gas
+// cells (Eq. equilempty) and the conversion of cells as they fill and empty
+// (flowchart of Sec. 4: stream the mass, redefine the cell classes).
+//
+// One step is five launches, plus one on moment steps:
+//   k_fs_step        pull + gas-side reconstruction + mass exchange + collision
+//                    of liquid and interface cells; conversion flags (w1) of
+//                    interface cells
+//   k_fs_mark_fill   filling cells mark their gas neighbours to become interface
+//                    cells and keep emptying neighbours
+//   k_fs_mark_empty  cells that empty mark their liquid neighbours to become
+//                    interface cells; marked gas cells get the equilibrium of
+//                    their neighbours' mean state
+//   k_fs_excess      excess mass of each converted cell, split over its receivers
+//   k_fs_final       new classes, masses and fill fractions
+//   k_fs_moments     moments and FP64 diagnostics (moment steps only)
+// Liquid cells cost one byte read and one byte written more than the
+// single-fluid step; gas cells are skipped (waves made only of gas cells
+// store nothing); the class passes read byte planes, 16 cells per thread, and
+// work only next to conversions.
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace plbm {
+
+enum { FS_GAS = 0, FS_IF = 1, FS_LIQ = 2, FS_SOLID = 3 };
+enum { FS_FILL = 1, FS_EMPTY = 2 };
+constexpr double FS_KAPPA = 1e-3;   // conversion margin: m > (1 + k) rho fills, m < -k rho empties
+
+// Free-surface state of one lattice, in its workspace.  Masses, densities
+// and fill fractions are double in every storage mode, so the class
+// decisions and the mass bookkeeping do not depend on the population format.
+struct FsDev {
+    unsigned char *cls;     // class of every cell after the last step (FS_*)
+    unsigned char *w1;      // step work bytes: conversion flag, then the packed new class
+    unsigned char *w2;      // step work bytes: resolved flag | 4 (gas cell to become interface)
+    double *mass;           // liquid mass m of interface cells
+    double *lam[2];         // fill fraction m / rho of interface cells, one plane per
+                            // population copy (pass 1 reads the neighbours' in the
+                            // source copy and writes its own in the other)
+    double *rho;            // rho and V' (3 planes) of the step: interface cells every
+    double *u;              // step, every liquid or interface cell on moment steps
+    double *share;          // excess mass per receiver of each converting cell
+    double *lost;           // accumulated excess mass that found no receiver
+};
+
+__device__ inline const FsDev *fs_of(const LatDev *L) { return static_cast<const FsDev *>(L->fs); }
+
+// f(std::integral_constant<int, Q>) for Q = 1 .. 18
+template <int Q = 1, class Fn>
+__device__ inline void for_links(Fn &&fn)
+{
+    fn(std::integral_constant<int, Q>{});
+    if constexpr (Q + 1 < NQ) for_links<Q + 1>(fn);
+}
+
+// the 19 populations of cell idx of one copy, decoded
+template <class S>
+__device__ inline void load_cell(const void *P, const void *M, uint32_t n, uint32_t idx, typename Codec<S>::R *o)
+{
+    using R = typename Codec<S>::R;
+    if constexpr (Codec<S>::split) {
+        const R m = ldg<R>(M, idx);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) o[q] = fma(weight<R>(q), m, Codec<S>::load(at(plane<S>(P, n, q), idx)));
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) o[q] = Codec<S>::load(at(plane<S>(P, n, q), idx));
+    }
+}
+
+// equilibrium deviations f^eq - w at (rho, u) (Eqs. equilc1/2 without the
+// surface-tension part): the collision with omega = 1 and no force of zeros
+template <class R>
+__device__ inline void equilibrium(R rho, const R u[3], R ie, R *e)
+{
+    const R zero3[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) e[q] = R(0);
+    const Coll<R> c = make_coll<R>(rho - R(1), rho, R(1), ie, u, zero3, R(0), zero3, R(0), R(0));
+    collide_f<R, false>(e, c);
+}
+
+struct FsCell {
+    const LatDev *L;
+    const FsDev *F;
+    int l, lb, flags;
+    uint32_t idx, ncell;
+};
+
+__device__ inline FsCell fs_cell(const BatchArgs &a)
+{
+    FsCell c;
+    const int gb = xcd_remap(blockIdx.x, a.total_blocks);
+    c.l = find_lattice(a, gb);
+    c.L = a.lat[c.l];
+    c.F = fs_of(c.L);
+    c.lb = slab_remap(gb - a.blk_start[c.l], c.L->bpp);
+    c.flags = a.flags[c.l];
+    c.ncell = c.L->ncell;
+    c.idx = uint32_t(c.lb) * BLOCK + threadIdx.x;
+    return c;
+}
+
+__device__ inline void coords(const LatDev *L, uint32_t idx, int &x, int &y, int &z)
+{
+    const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+    z = udiv(idx, L->div_nxy);
+    const uint32_t r = idx - uint32_t(z) * nxy;
+    y = udiv(r, L->div_nx);
+    x = r - uint32_t(y) * nx;
+}
+
+// Pass 1.  Liquid and interface cells: pull; on links from gas cells the
+// rebuilt population f_q = f^eq_q + f^eq_opp(q) - f~_opp(q)(x) at the gas
+// density 1 and the velocity of the cell's own post-collision populations
+// (Eq. equilempty); mass exchange over the links to liquid and interface
+// neighbours (Eq. deltamass); the single-fluid collision with the porous
+// terms; interface cells store m and rho and flag FILL / EMPTY.
+template <class S, bool FT>
+__global__ PLBM_STEP_ATTR void k_fs_step(const BatchArgs a)
+{
+    using R = typename Codec<S>::R;
+    const FsCell c = fs_cell(a);
+    const LatDev *__restrict__ L = c.L;
+    const FsDev *__restrict__ F = c.F;
+    const uint32_t idx = c.idx, ncell = c.ncell;
+    const int src = c.flags & 1, dst = src ^ 1;
+    const bool mom = (c.flags & 2) != 0;
+    const R nuc = R(a.nuc[c.l]);
+
+    int cls = FS_SOLID, x = 0, y = 0, z = 0;
+    uint32_t lw = 0;
+    if (idx < ncell) {
+        coords(L, idx, x, y, z);
+        lw = link_word(L, idx);
+        cls = ldg<uint8_t>(F->cls, idx);
+    }
+    const bool live = cls == FS_IF || cls == FS_LIQ;
+    R d[NQ];
+    unsigned char flag = 0;
+    if (live) {
+        const Nbr b = neighbours(L, x, y, z, lw);
+        pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
+        const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
+        const R ie = rcp(eps);
+        double m = 0.0;
+        if (cls == FS_IF) {
+            R o[NQ];
+            load_cell<S>(L->f[src], L->fm[src], L->pstride, idx, o);
+            R odr = 0, ojx = 0, ojy = 0, ojz = 0;
+            moments_acc<R>(o, odr, ojx, ojy, ojz);
+            const R iro = rcp(R(1) + odr);
+            const R ou[3] = {ojx * iro, ojy * iro, ojz * iro};
+            R eA[NQ];
+            equilibrium<R>(R(1), ou, ie, eA);
+            const double lx = ldg<double>(F->lam[src], idx);
+            double dm = 0.0;
+            for_links([&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
+                // the neighbour x - v_Q, whose population Q streams in and to
+                // which the population opp(Q) of this cell streams out
+                const uint32_t j = shifted<Q, -1>(b);
+                const int cj = shifted_solid<Q, -1>(b) ? FS_SOLID : int(ldg<uint8_t>(F->cls, j));
+                if (cj == FS_GAS) {
+                    d[Q] = eA[Q] + eA[opp(Q)] - o[opp(Q)];
+                } else if (cj != FS_SOLID) {
+                    const double fl = double(d[Q]) - double(o[opp(Q)]);
+                    dm += cj == FS_LIQ ? fl : fl * (0.5 * (lx + ldg<double>(F->lam[src], j)));
+                }
+            });
+            m = ldg<double>(F->mass, idx) + dm;
+        }
+
+        R drho = 0, jx = 0, jy = 0, jz = 0;
+        moments_acc<R>(d, drho, jx, jy, jz);
+        const R rho = R(1) + drho;
+        const R irho = rcp(rho);
+        const R V[3] = {jx * irho, jy * irho, jz * irho};
+        const R nu = nuc * fexp(R(L->k0));
+        const R omega = rcp(R(0.5) + R(3) * nu);
+        R u[3], Fx[3];
+        if constexpr (FT) {
+            const R q[4] = {ldg<R>(L->kinv, idx), ldp<R>(L->kinv, ncell, 1, idx), ldp<R>(L->kinv, ncell, 2, idx),
+                            ldp<R>(L->kinv, ncell, 3, idx)};
+            const R mu[3] = {ldp<R>(L->kinv, ncell, 4, idx), ldp<R>(L->kinv, ncell, 5, idx),
+                             ldp<R>(L->kinv, ncell, 6, idx)};
+            porous_force_frame<R>(L, eps, q, mu, nu, V, u, Fx);
+        } else {
+            R kinv[3];
+            if (L->uniform_kinv) {
+                kinv[0] = R(L->kinv_u[0]);
+                kinv[1] = R(L->kinv_u[1]);
+                kinv[2] = R(L->kinv_u[2]);
+            } else {
+                kinv[0] = ldg<R>(L->kinv, idx);
+                kinv[1] = ldp<R>(L->kinv, ncell, 1, idx);
+                kinv[2] = ldp<R>(L->kinv, ncell, 2, idx);
+            }
+            porous_force<R>(L, eps, kinv, nu, V, u, Fx);
+        }
+        const R zero3[3] = {0, 0, 0};
+        const Coll<R> cl = make_coll<R>(drho, rho, omega, ie, u, Fx, R(0), zero3, R(0), R(0));
+        collide_f<R, false>(d, cl);
+
+        if (cls == FS_IF) {
+            const double r = double(rho);
+            stg<double>(F->mass, idx, m);
+            stg<double>(F->rho, idx, r);
+            for (int k = 0; k < 3; ++k) stp<double>(F->u, ncell, k, idx, double(u[k]));
+            stg<double>(F->lam[dst], idx, m / r);   // before the shares of converting neighbours
+            stg<uint8_t>(F->w2, idx, 0);            // a mark of the last step
+            flag = m > (1.0 + FS_KAPPA) * r ? FS_FILL : (m < -FS_KAPPA * r ? FS_EMPTY : 0);
+        } else if (mom) {
+            stg<double>(F->rho, idx, double(rho));
+            for (int k = 0; k < 3; ++k) stp<double>(F->u, ncell, k, idx, double(u[k]));
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) d[q] = R(0);
+    }
+    if (idx < ncell) stg<uint8_t>(F->w1, idx, flag);
+    // waves made only of gas and solid cells store nothing
+    if (idx < ncell && __builtin_amdgcn_ballot_w64(live) != 0)
+        store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
+}
+
+// ---------------------------------------------------------------------------
+// The class passes touch only the few cells next to conversions.  Each thread
+// scans the bytes of FS_CPT consecutive cells with one 16-byte load per plane
+// (planes are 256-byte aligned and padded, so the last load of a lattice stays
+// inside its plane) and works only on the cells that need it; a cell's
+// neighbours are reached by writing into their mark bytes (w2), so no thread
+// has to look for conversions around itself.  Marks written by several cells
+// into one byte carry the same value.
+//   w1: the FILL / EMPTY flag of pass 1 (0 elsewhere)
+//   w2: FS_BORN (gas cell next to a filling cell), FS_KEEP (emptying cell next
+//       to a filling cell: it stays), FS_TO_IF (liquid cell next to a cell that
+//       empties), FS_RECV (a receiver of excess mass); zero outside the marked
+//       cells.  The last pass clears the marks of cells that were not interface
+//       cells (it reads FS_KEEP marks of neighbours, so those stay); pass 1 of
+//       the next step clears the marks of interface cells.
+constexpr int FS_CPT = 16;
+enum { FS_BORN = 1, FS_KEEP = 2, FS_TO_IF = 4, FS_RECV = 8 };
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct FsTile {
+    const LatDev *L;
+    const FsDev *F;
+    int flags;
+    uint32_t base, ncell;
+};
+
+// blocks of BLOCK * FS_CPT cells
+__device__ inline FsTile fs_tile(const BatchArgs &a)
+{
+    FsTile t;
+    const int gb = blockIdx.x;
+    const int l = find_lattice(a, gb);
+    t.L = a.lat[l];
+    t.F = fs_of(t.L);
+    t.flags = a.flags[l];
+    t.ncell = t.L->ncell;
+    t.base = (uint32_t(gb - a.blk_start[l]) * BLOCK + threadIdx.x) * FS_CPT;
+    return t;
+}
+
+__device__ inline u32x4 ld16(const unsigned char *p, uint32_t base) { return ldg<u32x4>(p, base / FS_CPT); }
+
+__device__ inline int byte_of(const u32x4 &v, int k)
+{
+    const uint32_t w = k < 4 ? v.x : (k < 8 ? v.y : (k < 12 ? v.z : v.w));
+    return int((w >> (8 * (k & 3))) & 0xffu);
+}
+
+__device__ inline bool any_byte(const u32x4 &v) { return (v.x | v.y | v.z | v.w) != 0u; }
+
+// the cell empties after all: flagged EMPTY and not kept by a filling neighbour
+__device__ inline bool empties(int w1, int w2) { return w1 == FS_EMPTY && !(w2 & FS_KEEP); }
+
+__device__ inline Nbr nbr_of(const LatDev *L, uint32_t idx)
+{
+    int x, y, z;
+    coords(L, idx, x, y, z);
+    return neighbours(L, x, y, z, 0u);
+}
+
+// Pass 2.  Every filling cell marks its gas neighbours FS_BORN and its
+// emptying neighbours FS_KEEP.
+__global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
+{
+    const FsTile t = fs_tile(a);
+    if (t.base >= t.ncell) return;
+    const FsDev *__restrict__ F = t.F;
+    const u32x4 f = ld16(F->w1, t.base);
+    if (!any_byte(f)) return;
+    for (int k = 0; k < FS_CPT; ++k) {
+        const uint32_t idx = t.base + k;
+        if (idx >= t.ncell || byte_of(f, k) != FS_FILL) continue;
+        const Nbr b = nbr_of(t.L, idx);
+        for_links([&](auto qc) {
+            constexpr int Q = decltype(qc)::value;
+            const uint32_t j = shifted<Q, 1>(b);
+            const int cj = ldg<uint8_t>(F->cls, j), fj = ldg<uint8_t>(F->w1, j);
+            if (cj == FS_GAS) stg<uint8_t>(F->w2, j, FS_BORN);
+            else if (fj == FS_EMPTY) stg<uint8_t>(F->w2, j, FS_KEEP);
+        });
+    }
+}
+
+// Pass 3.  Every cell that empties marks its liquid neighbours FS_TO_IF;
+// every FS_BORN cell takes the equilibrium of the mean density and velocity
+// of the post-collision populations of its liquid and interface neighbours
+// that do not empty, with m = 0.
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
+{
+    using R = typename Codec<S>::R;
+    const FsTile t = fs_tile(a);
+    if (t.base >= t.ncell) return;
+    const LatDev *__restrict__ L = t.L;
+    const FsDev *__restrict__ F = t.F;
+    const int dst = (t.flags & 1) ^ 1;
+    const bool mom = (t.flags & 2) != 0;
+    const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
+    if (!any_byte(f) && !any_byte(m2)) return;
+    for (int k = 0; k < FS_CPT; ++k) {
+        const uint32_t idx = t.base + k;
+        if (idx >= t.ncell) break;
+        const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
+        if (empties(w1, w2)) {
+            const Nbr b = nbr_of(L, idx);
+            for_links([&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
+                const uint32_t j = shifted<Q, 1>(b);
+                if (ldg<uint8_t>(F->cls, j) == FS_LIQ) stg<uint8_t>(F->w2, j, FS_TO_IF);
+            });
+        } else if (w2 & FS_BORN) {
+            // a gas cell has no liquid neighbour: the qualifying neighbours are
+            // interface cells, whose rho and V' pass 1 stored
+            const Nbr b = nbr_of(L, idx);
+            double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
+            int n = 0;
+            for_links([&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
+                const uint32_t j = shifted<Q, 1>(b);
+                // an interface neighbour's mark byte is not written in this pass
+                if (ldg<uint8_t>(F->cls, j) == FS_IF && !empties(ldg<uint8_t>(F->w1, j), ldg<uint8_t>(F->w2, j))) {
+                    rs += ldg<double>(F->rho, j);
+                    for (int c = 0; c < 3; ++c) us[c] += ldp<double>(F->u, t.ncell, c, j);
+                    ++n;
+                }
+            });
+            // n >= 1: the filling neighbour qualifies
+            const double in = n ? 1.0 / n : 0.0;
+            const double ra = n ? rs * in : 1.0;
+            const double ua[3] = {us[0] * in, us[1] * in, us[2] * in};
+            const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
+            const R ur[3] = {R(ua[0]), R(ua[1]), R(ua[2])};
+            R e[NQ];
+            equilibrium<R>(R(ra), ur, rcp(eps), e);
+            store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, e);
+            stg<double>(F->mass, idx, 0.0);
+            stg<double>(F->rho, idx, ra);
+            for (int c = 0; c < 3; ++c) stp<double>(F->u, t.ncell, c, idx, ua[c]);
+        }
+    }
+}
+
+// does the neighbour j convert (fill, or empty after all)?
+__device__ inline bool converts(const FsDev *F, uint32_t j)
+{
+    const int f = ldg<uint8_t>(F->w1, j);
+    return f == FS_FILL || (f == FS_EMPTY && !(ldg<uint8_t>(F->w2, j) & FS_KEEP));
+}
+
+// Pass 4.  Excess mass of each converted cell (m - rho when it filled, m when
+// it emptied), split equally over its neighbours that end the step as
+// interface cells without converting; without any, it is lost (and counted).
+__global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
+{
+    const FsTile t = fs_tile(a);
+    if (t.base >= t.ncell) return;
+    const FsDev *__restrict__ F = t.F;
+    const u32x4 f = ld16(F->w1, t.base);
+    if (!any_byte(f)) return;
+    const u32x4 m2 = ld16(F->w2, t.base);
+    for (int k = 0; k < FS_CPT; ++k) {
+        const uint32_t idx = t.base + k;
+        if (idx >= t.ncell) break;
+        const int w1 = byte_of(f, k);
+        if (!(w1 == FS_FILL || empties(w1, byte_of(m2, k)))) continue;
+        const Nbr b = nbr_of(t.L, idx);
+        int n = 0;
+        for_links([&](auto qc) {
+            constexpr int Q = decltype(qc)::value;
+            const uint32_t j = shifted<Q, 1>(b);
+            const int cj = ldg<uint8_t>(F->cls, j), mj = ldg<uint8_t>(F->w2, j);
+            const bool recv = (cj == FS_IF && !converts(F, j)) || (mj & (FS_BORN | FS_TO_IF));
+            n += recv ? 1 : 0;
+        });
+        const double m = ldg<double>(F->mass, idx);
+        const double ex = w1 == FS_FILL ? m - ldg<double>(F->rho, idx) : m;
+        stg<double>(F->share, idx, n ? ex / n : 0.0);
+        if (!n) atomicAdd(F->lost, ex);
+        // mark the receivers: every writer of a mark byte writes the same value
+        // (the other bits do not change in this pass)
+        if (n)
+            for_links([&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
+                const uint32_t j = shifted<Q, 1>(b);
+                const int cj = ldg<uint8_t>(F->cls, j), mj = ldg<uint8_t>(F->w2, j);
+                if ((cj == FS_IF && !converts(F, j)) || (mj & (FS_BORN | FS_TO_IF)))
+                    stg<uint8_t>(F->w2, j, (uint8_t)(mj | FS_RECV));
+            });
+    }
+}
+
+// Pass 5.  New classes of the converted and marked cells; the final mass and
+// fill fraction of the interface cells that changed: their own mass (rho for
+// a liquid cell that became one, 0 for a gas cell that did) plus the shares
+// of their converting neighbours (FS_RECV cells only); marks of cells that
+// were not interface cells cleared.  The fill fraction of every other
+// interface cell was written by pass 1.
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
+{
+    using R = typename Codec<S>::R;
+    const FsTile t = fs_tile(a);
+    if (t.base >= t.ncell) return;
+    const LatDev *__restrict__ L = t.L;
+    const FsDev *__restrict__ F = t.F;
+    const int dst = (t.flags & 1) ^ 1;
+    const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
+    if (!any_byte(f) && !any_byte(m2)) return;
+    for (int k = 0; k < FS_CPT; ++k) {
+        const uint32_t idx = t.base + k;
+        if (idx >= t.ncell) break;
+        const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
+        if (!w1 && !w2) continue;
+        if (w1 == FS_FILL) {
+            stg<uint8_t>(F->cls, idx, FS_LIQ);
+            continue;
+        }
+        if (empties(w1, w2)) {
+            stg<uint8_t>(F->cls, idx, FS_GAS);
+            continue;
+        }
+        if (!(w2 & (FS_BORN | FS_TO_IF | FS_RECV))) continue;   // kept, no share
+        double m, r;
+        if (w2 & FS_BORN) {
+            m = 0.0;
+            r = ldg<double>(F->rho, idx);
+        } else if (w2 & FS_TO_IF) {     // a liquid cell: m = its density
+            R o[NQ];
+            load_cell<S>(L->f[dst], L->fm[dst], L->pstride, idx, o);
+            R dr = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) dr += o[q];
+            r = 1.0 + double(dr);
+            m = r;
+        } else {
+            m = ldg<double>(F->mass, idx);
+            r = ldg<double>(F->rho, idx);
+        }
+        if (w2 & FS_RECV) {
+            const Nbr b = nbr_of(L, idx);
+            for_links([&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
+                const uint32_t j = shifted<Q, 1>(b);
+                if (converts(F, j)) m += ldg<double>(F->share, j);
+            });
+        }
+        stg<double>(F->mass, idx, m);
+        stg<double>(F->lam[dst], idx, m / r);
+        if (w2 & (FS_BORN | FS_TO_IF)) {
+            stg<uint8_t>(F->cls, idx, FS_IF);
+            stg<uint8_t>(F->w2, idx, 0);
+        }
+    }
+}
+
+// Moment steps, after pass 5 (one thread per cell, the step grid): rho, V'
+// and lambda of the step into the moments buffer (gas and solid cells 0) and
+// the FP64 diagnostic partials over liquid and interface cells, with
+// diag[4] = the liquid mass (m of interface cells, rho of liquid cells).
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_fs_moments(const BatchArgs a)
+{
+    using R = typename Codec<S>::R;
+    const FsCell c = fs_cell(a);
+    const LatDev *__restrict__ L = c.L;
+    const FsDev *__restrict__ F = c.F;
+    const uint32_t idx = c.idx, ncell = c.ncell;
+    const int dst = (c.flags & 1) ^ 1;
+    double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (idx < ncell) {
+        const int nt = ldg<uint8_t>(F->cls, idx);
+        const bool live = nt == FS_IF || nt == FS_LIQ;
+        void *M = L->mom;
+        R rho = 0, u[3] = {0, 0, 0}, lam = 0;
+        double m = 0.0;
+        if (live) {
+            rho = R(ldg<double>(F->rho, idx));
+            for (int k = 0; k < 3; ++k) u[k] = R(ldp<double>(F->u, ncell, k, idx));
+            lam = nt == FS_LIQ ? R(1) : R(ldg<double>(F->lam[dst], idx));
+            m = nt == FS_LIQ ? ldg<double>(F->rho, idx) : ldg<double>(F->mass, idx);
+        }
+        const R up[3] = {ldp<R>(M, ncell, 1, idx), ldp<R>(M, ncell, 2, idx), ldp<R>(M, ncell, 3, idx)};
+        stg<R>(M, idx, rho);
+        stp<R>(M, ncell, 1, idx, u[0]);
+        stp<R>(M, ncell, 2, idx, u[1]);
+        stp<R>(M, ncell, 3, idx, u[2]);
+        stp<R>(M, ncell, 4, idx, lam);
+        if (live) {
+            diag_contrib<R>(part, rho, u, lam, R(0), up);
+            part[4] = m;
+        }
+    }
+    block_reduce_store(part, L->partials + size_t(c.lb) * NPART);
+}
+
+// ---------------------------------------------------------------------------
+// set-up: classes from the initial fill fraction c0 (>= 1 liquid, <= 0 gas,
+// else interface), then liquid cells next to gas cells become interface
+// cells; masses m = lambda rho0, fill fractions, the moments of step 0
+// (gas cells read 0) and their diagnostics.
+
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_fs_init_classes(const LatDev *L, const R *c0)
+{
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= uint32_t(L->ncell)) return;
+    const FsDev *F = fs_of(L);
+    int x, y, z, face;
+    coords(L, idx, x, y, z);
+    const int type = cell_type(L, x, y, z, link_word(L, idx), face);
+    const R l = c0 ? c0[idx] : R(0);
+    stg<uint8_t>(F->w1, idx, type != CELL_FLUID ? FS_SOLID : (l >= R(1) ? FS_LIQ : (l <= R(0) ? FS_GAS : FS_IF)));
+}
+
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const R *c0, const R *rho0)
+{
+    const uint32_t ncell = L->ncell;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (idx < ncell) {
+        const FsDev *F = fs_of(L);
+        int cls = ldg<uint8_t>(F->w1, idx);
+        if (cls == FS_LIQ) {
+            int x, y, z;
+            coords(L, idx, x, y, z);
+            const Nbr b = neighbours(L, x, y, z, 0u);
+            bool near_gas = false;
+            for_links([&](auto qc) {
+                constexpr int Q = decltype(qc)::value;
+                near_gas = near_gas || ldg<uint8_t>(F->w1, shifted<Q, 1>(b)) == FS_GAS;
+            });
+            if (near_gas) cls = FS_IF;
+        }
+        const double r0 = rho0 ? double(rho0[idx]) : 1.0;
+        double l = c0 ? double(c0[idx]) : 0.0;
+        l = cls == FS_LIQ ? 1.0 : (cls == FS_IF ? fmin(fmax(l, 0.0), 1.0) : 0.0);
+        stg<uint8_t>(F->cls, idx, (unsigned char)cls);
+        stg<uint8_t>(F->w2, idx, 0);
+        stg<double>(F->lam[0], idx, l);
+        stg<double>(F->lam[1], idx, l);
+        stg<double>(F->mass, idx, l * r0);
+        stg<double>(F->rho, idx, cls == FS_IF || cls == FS_LIQ ? r0 : 0.0);
+        void *M = L->mom;
+        const bool live = cls == FS_IF || cls == FS_LIQ;
+        if (!live) {
+            stg<R>(M, idx, R(0));
+            for (int k = 1; k < 4; ++k) stp<R>(M, ncell, k, idx, R(0));
+        }
+        stp<R>(M, ncell, 4, idx, R(l));
+        if (live) {
+            const R u[3] = {ldp<R>(M, ncell, 1, idx), ldp<R>(M, ncell, 2, idx), ldp<R>(M, ncell, 3, idx)};
+            diag_contrib<R>(part, ldg<R>(M, idx), u, R(l), R(0), u);
+            part[4] = l * r0;
+        }
+    }
+    block_reduce_store(part, L->partials + size_t(blockIdx.x) * NPART);
+}
+
+// classes and masses for lbm_free_surface: m of interface cells, rho (from
+// the current populations) of liquid cells, 0 elsewhere
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_fs_export(const LatDev *L, int src, unsigned char *cls, double *mass)
+{
+    using R = typename Codec<S>::R;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= uint32_t(L->ncell)) return;
+    const FsDev *F = fs_of(L);
+    const int c = ldg<uint8_t>(F->cls, idx);
+    if (cls) cls[idx] = (unsigned char)c;
+    if (mass) {
+        double m = 0.0;
+        if (c == FS_IF) {
+            m = ldg<double>(F->mass, idx);
+        } else if (c == FS_LIQ) {
+            R o[NQ];
+            load_cell<S>(L->f[src], L->fm[src], L->pstride, idx, o);
+            R dr = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) dr += o[q];
+            m = 1.0 + double(dr);
+        }
+        mass[idx] = m;
+    }
+}
+
+}  // namespace plbm

@@ -26,7 +26,7 @@
 
 namespace plbm {
 
-enum { PH_SINGLE = 0, PH_MISCIBLE = 1, PH_IMMISCIBLE = 2 };
+enum { PH_SINGLE = 0, PH_MISCIBLE = 1, PH_IMMISCIBLE = 2, PH_FREESURF = 3 };
 enum { CELL_FLUID = 0, CELL_SOLID = 1, CELL_RES = 2 };
 
 #ifndef PLBM_BLOCK
@@ -75,6 +75,7 @@ struct LatDev {
     void *fm[2], *hm[2];        // split 16-bit codecs: per-cell FP32 mass planes of each copy
     void *eps, *kinv, *mom, *rho1;
     const void *links;          // obstacle mask as link words (bit 0: solid, bit q: x - v_q solid), or null
+    const void *fs;             // free-surface state (FsDev), or null
     double *partials, *diag;
     int *err;
     uint32_t div_nx[3], div_nxy[3];   // magic numbers of the divisions by nx and nx*ny

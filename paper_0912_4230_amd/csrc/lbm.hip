@@ -11,6 +11,7 @@
 #include <new>
 
 #include "kernels.hpp"
+#include "freesurf.hpp"
 
 using namespace plbm;
 
@@ -46,10 +47,14 @@ size_t plane_stride(const lbm_desc *d)
 }
 
 struct Layout {
-    size_t lat, err, diag, partials, eps, kinv, mom, rho1, links, f0, f1, h0, h1, fm0, fm1, hm0, hm1, total;
+    size_t lat, err, diag, partials, eps, kinv, mom, rho1, links, f0, f1, h0, h1, fm0, fm1, hm0, hm1;
+    size_t fs, fs_cls, fs_w1, fs_w2, fs_mass, fs_lam, fs_rho, fs_share, fs_u, total;
 };
 
 bool split_storage(int storage) { return storage == LBM_BF16_SPLIT || storage == LBM_F16_SPLIT; }
+
+// a second lattice (solute or fluid 1)
+bool two_lattices(int physics) { return physics == LBM_MISCIBLE || physics == LBM_IMMISCIBLE; }
 
 bool is_fin(double v) { return isfinite(v) != 0; }
 
@@ -64,7 +69,13 @@ bool valid_desc(const lbm_desc *d)
     // field plane, or a pair of population planes for the bounce-back selects
     const unsigned long long pair = 2ULL * plane_stride(d) * storage_bytes(d->storage);
     if ((unsigned long long)ncell * real_bytes(d->storage) > (1ULL << 32) || pair > (1ULL << 32)) return false;
-    if (d->physics < LBM_SINGLE || d->physics > LBM_IMMISCIBLE) return false;
+    if (d->physics < LBM_SINGLE || d->physics > LBM_FREESURF) return false;
+    // free surface: per-cell doubles addressed by 32-bit byte offsets; no reservoirs
+    if (d->physics == LBM_FREESURF) {
+        if ((unsigned long long)ncell * 8ULL > (1ULL << 32)) return false;
+        for (int f = 0; f < 6; ++f)
+            if (d->face[f].kind == LBM_FACE_RESERVOIR) return false;
+    }
     if (d->storage < LBM_F64 || d->storage > LBM_F16_SPLIT) return false;
     const int n[3] = {d->nx, d->ny, d->nz};
     for (int a = 0; a < 3; ++a) {
@@ -119,13 +130,26 @@ Layout layout(const lbm_desc *d)
     const size_t ps = plane_stride(d);
     L.f0 = o;        o = align_up(o + NQ * ps * sb);
     L.f1 = o;        o = align_up(o + NQ * ps * sb);
-    L.h0 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * ps * sb);
-    L.h1 = o;        if (d->physics != LBM_SINGLE) o = align_up(o + NQ * ps * sb);
-    const bool sp = split_storage(d->storage), two = d->physics != LBM_SINGLE;
+    const bool sp = split_storage(d->storage), two = two_lattices(d->physics);
+    L.h0 = o;        if (two) o = align_up(o + NQ * ps * sb);
+    L.h1 = o;        if (two) o = align_up(o + NQ * ps * sb);
     L.fm0 = o;       if (sp) o = align_up(o + n * sizeof(float));
     L.fm1 = o;       if (sp) o = align_up(o + n * sizeof(float));
     L.hm0 = o;       if (sp && two) o = align_up(o + n * sizeof(float));
     L.hm1 = o;       if (sp && two) o = align_up(o + n * sizeof(float));
+    const bool fs = d->physics == LBM_FREESURF;
+    // free surface: the FsDev block (+ the lost-mass counter), three byte
+    // planes, five double planes (m, two of lambda, rho, share) and the 3
+    // double planes of V'
+    L.fs = o;        if (fs) o = align_up(o + sizeof(FsDev) + sizeof(double));
+    L.fs_cls = o;    if (fs) o = align_up(o + n);
+    L.fs_w1 = o;     if (fs) o = align_up(o + n);
+    L.fs_w2 = o;     if (fs) o = align_up(o + n);
+    L.fs_mass = o;   if (fs) o = align_up(o + n * sizeof(double));
+    L.fs_lam = o;    if (fs) o = align_up(o + 2 * n * sizeof(double));
+    L.fs_rho = o;    if (fs) o = align_up(o + n * sizeof(double));
+    L.fs_share = o;  if (fs) o = align_up(o + n * sizeof(double));
+    L.fs_u = o;      if (fs) o = align_up(o + 3 * n * sizeof(double));
     L.total = o;
     return L;
 }
@@ -159,6 +183,7 @@ struct lbm_sim {
     size_t ws_bytes;
     Layout lay;
     LatDev host;        // host copy of the device parameter block
+    FsDev fs;           // host copy of the free-surface block (free surface only)
     LatDev *dev;        // the device parameter block (inside ws)
     long long steps;    // completed steps
     int cur;            // copy holding the current state
@@ -210,6 +235,44 @@ Launch step_for_tensor(int storage, bool full_tensor)
     return full_tensor ? step_for_storage<P, true>(storage) : step_for_storage<P, false>(storage);
 }
 
+// Free surface: the stream/collide pass on the step grid (a), the class
+// passes on the grid of BLOCK * FS_CPT cells per block (a16), the moments
+// pass on the step grid of the lattices at a moment step (am, may be empty).
+struct FsGrids {
+    BatchArgs a, a16, am;
+    int blocks, blocks16, blocksm;
+};
+
+#ifndef PLBM_FS_LDS
+#define PLBM_FS_LDS 0
+#endif
+
+template <class S, bool FT>
+void launch_fs(const FsGrids &g, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fs_step<S, FT>), dim3(g.blocks), dim3(BLOCK), PLBM_FS_LDS, s, g.a);
+    hipLaunchKernelGGL(k_fs_mark_fill, dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
+    hipLaunchKernelGGL((k_fs_mark_empty<S>), dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
+    hipLaunchKernelGGL(k_fs_excess, dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
+    hipLaunchKernelGGL((k_fs_final<S>), dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
+    if (g.blocksm) hipLaunchKernelGGL((k_fs_moments<S>), dim3(g.blocksm), dim3(BLOCK), 0, s, g.am);
+}
+
+using FsLaunch = void (*)(const FsGrids &, hipStream_t);
+
+template <bool FT>
+FsLaunch fs_for_storage(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return launch_fs<double, FT>;
+    case LBM_F32: return launch_fs<float, FT>;
+    case LBM_BF16_DEV: return launch_fs<bf16_t, FT>;
+    case LBM_F16_DEV: return launch_fs<f16_t, FT>;
+    case LBM_BF16_SPLIT: return launch_fs<bf16s_t, FT>;
+    default: return launch_fs<f16s_t, FT>;
+    }
+}
+
 Launch step_launcher(int physics, int storage, bool full_tensor)
 {
     switch (physics) {
@@ -245,6 +308,36 @@ void launch_init(const lbm_sim *h, const lbm_medium *m, int blocks)
         hipLaunchKernelGGL((k_init_colour<R>), dim3(blocks), dim3(BLOCK), 0, h->stream, ia);
     hipLaunchKernelGGL((k_init<P, S>), dim3(blocks), dim3(BLOCK), 0, h->stream, ia);
     hipLaunchKernelGGL((k_diag_moments<R>), dim3(blocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev);
+}
+
+// free surface: the single-fluid set-up of the populations, then the classes,
+// masses and fill fractions, the moments of step 0 and their diagnostic partials
+template <class S>
+void launch_fs_init(const lbm_sim *h, const lbm_medium *m, int blocks)
+{
+    using R = typename Codec<S>::R;
+    InitArgs<R> ia;
+    ia.L = h->dev;
+    ia.rho0 = static_cast<const R *>(m->rho0);
+    ia.vel0 = static_cast<const R *>(m->vel0);
+    ia.c0 = static_cast<const R *>(m->c0);
+    ia.nuc0 = h->d.nu0 * time_factor(&h->d, 0.0);
+    const LatDev *L = h->dev;
+    hipLaunchKernelGGL((k_init<PH_SINGLE, S>), dim3(blocks), dim3(BLOCK), 0, h->stream, ia);
+    hipLaunchKernelGGL(k_fs_init_classes<R>, dim3(blocks), dim3(BLOCK), 0, h->stream, L, ia.c0);
+    hipLaunchKernelGGL(k_fs_init_state<R>, dim3(blocks), dim3(BLOCK), 0, h->stream, L, ia.c0, ia.rho0);
+}
+
+void fs_init(const lbm_sim *h, const lbm_medium *m, int blocks)
+{
+    switch (h->d.storage) {
+    case LBM_F64: launch_fs_init<double>(h, m, blocks); break;
+    case LBM_F32: launch_fs_init<float>(h, m, blocks); break;
+    case LBM_BF16_DEV: launch_fs_init<bf16_t>(h, m, blocks); break;
+    case LBM_F16_DEV: launch_fs_init<f16_t>(h, m, blocks); break;
+    case LBM_BF16_SPLIT: launch_fs_init<bf16s_t>(h, m, blocks); break;
+    default: launch_fs_init<f16s_t>(h, m, blocks); break;
+    }
 }
 
 template <int P>
@@ -292,8 +385,42 @@ lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
     a.blk_start[n] = total;
     a.total_blocks = total;
     const lbm_sim *h0 = hs[0];
-    if (h0->d.physics == LBM_IMMISCIBLE) colour_launcher(h0->d.storage)(a, total, h0->stream);
-    step_launcher(h0->d.physics, h0->d.storage, h0->host.full_tensor != 0)(a, total, h0->stream);
+    if (h0->d.physics == LBM_FREESURF) {
+        FsGrids g;
+        g.a = a;
+        g.blocks = total;
+        memset(&g.a16, 0, sizeof(g.a16));
+        memset(&g.am, 0, sizeof(g.am));
+        int t16 = 0, tm = 0, nm = 0;
+        for (int i = 0; i < n; ++i) {
+            const lbm_sim *h = hs[i];
+            const int nb16 = (h->host.ncell + BLOCK * FS_CPT - 1) / (BLOCK * FS_CPT);
+            g.a16.blk_start[i] = t16;
+            g.a16.lat[i] = h->dev;
+            g.a16.flags[i] = a.flags[i];
+            t16 += nb16;
+            if (a.flags[i] & 2) {
+                g.am.blk_start[nm] = tm;
+                g.am.lat[nm] = h->dev;
+                g.am.flags[nm] = a.flags[i];
+                tm += h->nblocks;
+                ++nm;
+            }
+        }
+        g.a16.n = n;
+        g.a16.blk_start[n] = t16;
+        g.a16.total_blocks = t16;
+        g.am.n = nm;
+        g.am.blk_start[nm] = tm;
+        g.am.total_blocks = tm;
+        g.blocks16 = t16;
+        g.blocksm = tm;
+        const bool ft = h0->host.full_tensor != 0;
+        (ft ? fs_for_storage<true>(h0->d.storage) : fs_for_storage<false>(h0->d.storage))(g, h0->stream);
+    } else {
+        if (h0->d.physics == LBM_IMMISCIBLE) colour_launcher(h0->d.storage)(a, total, h0->stream);
+        step_launcher(h0->d.physics, h0->d.storage, h0->host.full_tensor != 0)(a, total, h0->stream);
+    }
     if (ndiag) {
         diag.n = ndiag;
         hipLaunchKernelGGL(k_diag_final, dim3(ndiag), dim3(BLOCK), 0, h0->stream, diag);
@@ -382,9 +509,9 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     char *w = h->ws;
     D.f[0] = w + L.f0;
     D.f[1] = w + L.f1;
-    D.h[0] = d->physics != LBM_SINGLE ? w + L.h0 : nullptr;
-    D.h[1] = d->physics != LBM_SINGLE ? w + L.h1 : nullptr;
-    const bool sp = split_storage(d->storage), two = d->physics != LBM_SINGLE;
+    const bool sp = split_storage(d->storage), two = two_lattices(d->physics);
+    D.h[0] = two ? w + L.h0 : nullptr;
+    D.h[1] = two ? w + L.h1 : nullptr;
     D.fm[0] = sp ? w + L.fm0 : nullptr;
     D.fm[1] = sp ? w + L.fm1 : nullptr;
     D.hm[0] = sp && two ? w + L.hm0 : nullptr;
@@ -394,6 +521,20 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     D.mom = w + L.mom;
     D.rho1 = d->physics == LBM_IMMISCIBLE ? w + L.rho1 : nullptr;
     D.links = d->solid_mask ? w + L.links : nullptr;
+    if (d->physics == LBM_FREESURF) {
+        FsDev &F = h->fs;
+        F.cls = reinterpret_cast<unsigned char *>(w + L.fs_cls);
+        F.w1 = reinterpret_cast<unsigned char *>(w + L.fs_w1);
+        F.w2 = reinterpret_cast<unsigned char *>(w + L.fs_w2);
+        F.mass = reinterpret_cast<double *>(w + L.fs_mass);
+        F.lam[0] = reinterpret_cast<double *>(w + L.fs_lam);
+        F.lam[1] = F.lam[0] + n;
+        F.rho = reinterpret_cast<double *>(w + L.fs_rho);
+        F.share = reinterpret_cast<double *>(w + L.fs_share);
+        F.u = reinterpret_cast<double *>(w + L.fs_u);
+        F.lost = reinterpret_cast<double *>(w + L.fs + sizeof(FsDev));
+        D.fs = w + L.fs;
+    }
     D.partials = reinterpret_cast<double *>(w + L.partials);
     D.diag = reinterpret_cast<double *>(w + L.diag);
     D.err = reinterpret_cast<int *>(w + L.err);
@@ -423,6 +564,14 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     if ((st = dev_err(hipMemcpyAsync(h->dev, &D, sizeof(LatDev), hipMemcpyHostToDevice, h->stream)))) return st;
     static const int zero = 0;
     if ((st = dev_err(hipMemcpyAsync(D.err, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream)))) return st;
+    if (D.fs) {
+        static const double zero_mass = 0.0;
+        if ((st = dev_err(hipMemcpyAsync(const_cast<void *>(D.fs), &h->fs, sizeof(FsDev), hipMemcpyHostToDevice,
+                                         h->stream))))
+            return st;
+        if ((st = dev_err(hipMemcpyAsync(h->fs.lost, &zero_mass, sizeof(double), hipMemcpyHostToDevice, h->stream))))
+            return st;
+    }
     if (m->eps && (st = dev_err(hipMemcpyAsync(D.eps, m->eps, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
     if (m->kinv && !D.full_tensor &&
         (st = dev_err(hipMemcpyAsync(D.kinv, m->kinv, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream))))
@@ -441,6 +590,7 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     }
     switch (h->d.physics) {
     case LBM_SINGLE: init_for_storage<PH_SINGLE>(h, m, h->nblocks); break;
+    case LBM_FREESURF: fs_init(h, m, h->nblocks); break;
     case LBM_MISCIBLE: init_for_storage<PH_MISCIBLE>(h, m, h->nblocks); break;
     default: init_for_storage<PH_IMMISCIBLE>(h, m, h->nblocks); break;
     }
@@ -495,7 +645,7 @@ lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n)
     bool last[MAXB];
     for (int s = 0; s < maxs; ++s) {
         // group the lattices still running by (physics, storage, permeability form)
-        for (int phys = LBM_SINGLE; phys <= LBM_IMMISCIBLE; ++phys)
+        for (int phys = LBM_SINGLE; phys <= LBM_FREESURF; ++phys)
             for (int grp_key = 0; grp_key < 2 * (LBM_F16_SPLIT + 1); ++grp_key) {
                 const int stg = grp_key >> 1, ft = grp_key & 1;
                 int k = 0;
@@ -542,7 +692,7 @@ lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8
 lbm_status lbm_populations(lbm_t h, int lattice, void *dst)
 {
     if (!h || !dst || lattice < 0 || lattice > 1) return LBM_EINVAL;
-    if (lattice == 1 && h->d.physics == LBM_SINGLE) return LBM_EINVAL;
+    if (lattice == 1 && !two_lattices(h->d.physics)) return LBM_EINVAL;
     if (!h->ready) return LBM_ESTATE;
     if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
     const LatDev *L = h->dev;
@@ -569,6 +719,31 @@ lbm_status lbm_populations(lbm_t h, int lattice, void *dst)
     lbm_status st;
     if ((st = dev_err(hipGetLastError()))) return st;
     return dev_err(hipStreamSynchronize(h->stream));
+}
+
+lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lost)
+{
+    if (!h || h->d.physics != LBM_FREESURF) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    const LatDev *L = h->dev;
+    if (cls || mass) {
+        switch (h->d.storage) {
+        case LBM_F64: hipLaunchKernelGGL(k_fs_export<double>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        case LBM_F32: hipLaunchKernelGGL(k_fs_export<float>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        case LBM_BF16_DEV: hipLaunchKernelGGL(k_fs_export<bf16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        case LBM_F16_DEV: hipLaunchKernelGGL(k_fs_export<f16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        case LBM_BF16_SPLIT: hipLaunchKernelGGL(k_fs_export<bf16s_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        default: hipLaunchKernelGGL(k_fs_export<f16s_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        }
+    }
+    lbm_status st;
+    if ((st = dev_err(hipGetLastError()))) return st;
+    double lo = 0.0;
+    if ((st = dev_err(hipMemcpyAsync(&lo, h->fs.lost, sizeof(double), hipMemcpyDeviceToHost, h->stream)))) return st;
+    if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
+    if (lost) *lost = lo;
+    return LBM_OK;
 }
 
 long long lbm_steps_done(lbm_t h) { return h ? h->steps : -1; }

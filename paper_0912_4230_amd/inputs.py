@@ -287,7 +287,9 @@ def falling_drop(shape=(140, 140, 1), radius=8.0, centre=None, G=1e-6, tau=0.7, 
     every other face periodic; no porous medium (eps = 1, K^-1 = 0).  The
     fill fraction of a cell is its covered volume estimated on a 4^3
     subgrid, so the drop's initial liquid mass is close to pi R^2 (or
-    4 pi R^3 / 3) for any centre."""
+    4 pi R^3 / 3) for any centre.  The high face of the fall axis is a wall
+    too (both faces of an axis are periodic or neither); the drop never
+    reaches it."""
     nx, ny, nz = shape
     if centre is None:
         centre = [nx / 2.0, ny / 2.0, nz / 2.0]
@@ -313,6 +315,7 @@ def falling_drop(shape=(140, 140, 1), radius=8.0, centre=None, G=1e-6, tau=0.7, 
     faces = [Face() for _ in range(6)]
     if wall:
         faces[2 * axis] = Face(kind=WALL)
+        faces[2 * axis + 1] = Face(kind=WALL)
     p = Problem(shape=tuple(shape), physics=FREESURF, G=tuple(g), nu0=(tau - 0.5) / 3.0,
                 faces=faces, c0=frac, vel0=vel0)
     return p.fill_defaults()
@@ -320,16 +323,39 @@ def falling_drop(shape=(140, 140, 1), radius=8.0, centre=None, G=1e-6, tau=0.7, 
 
 def pool(shape=(6, 5, 40), depth=20.5, G=1e-4, tau=0.8) -> Problem:
     """Free-surface liquid pool at rest: liquid up to the height `depth`
-    (the cell straddling it partly filled) above a wall at z = 0, gas above,
-    gravity G toward -z, periodic in x and y."""
+    (the cell straddling it partly filled) above a wall at z = 0, gas above
+    up to a wall at z = nz - 1, gravity G toward -z, periodic in x and y."""
     nx, ny, nz = shape
     zc = np.arange(nz, dtype=np.float64)[:, None, None] * np.ones((nz, ny, nx))
     # the wall cell z = 0 is solid; liquid fills from its face z = 0.5 upward
     c0 = np.clip(depth - (zc - 0.5), 0.0, 1.0)
     faces = [Face() for _ in range(6)]
     faces[4] = Face(kind=WALL)
+    faces[5] = Face(kind=WALL)
     p = Problem(shape=tuple(shape), physics=FREESURF, G=(0.0, 0.0, -G), nu0=(tau - 0.5) / 3.0,
                 faces=faces, c0=c0)
+    return p.fill_defaults()
+
+
+def penetration(shape=(256, 256, 256), seed=0, G=1e-4, k_ref=1.0, ratio=100.0, tau=0.8,
+                ring_angle=None) -> Problem:
+    """Liquid penetrating an unsaturated porous medium (the set-up of Sec. 5.5
+    in 3D, without its unprinted parameters): the spruce-like medium fills
+    the box, liquid fills the upper half y >= ny/2 and gas the pores below,
+    gravity G toward -y (along the grain), walls on both y faces, periodic in
+    x and z, Darcy + Forchheimer drag."""
+    nx, ny, nz = shape
+    if ring_angle is None:
+        eps, kinv = spruce_medium(shape, seed=seed, ratio=ratio, k_ref=k_ref)
+    else:
+        eps, kinv = inclined_spruce_medium(shape, seed=seed, ratio=ratio, angle_deg=ring_angle, k_ref=k_ref)
+    y = np.arange(ny)[None, :, None] * np.ones((nz, ny, nx))
+    c0 = (y >= ny // 2).astype(np.float64)
+    faces = [Face() for _ in range(6)]
+    faces[2] = Face(kind=WALL)
+    faces[3] = Face(kind=WALL)
+    p = Problem(shape=tuple(shape), physics=FREESURF, G=(0.0, -G, 0.0), forchheimer=True,
+                nu0=(tau - 0.5) / 3.0, faces=faces, eps=eps, kinv=kinv, c0=c0)
     return p.fill_defaults()
 
 

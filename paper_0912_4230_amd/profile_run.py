@@ -5,7 +5,7 @@
 
 `step` sets up one lattice of the chosen workload and runs the given number
 of steps (one step kernel launch each, plus the colour pass in two-fluid
-mode); `copy` runs torch's device-to-device copy of a buffer of known size,
+mode, or the five launches of a free-surface step); `copy` runs torch's device-to-device copy of a buffer of known size,
 the reference kernel used to scale the FETCH_SIZE / WRITE_SIZE counters to
 bytes.  Both print what they ran, with the byte counts of one launch.
 """
@@ -27,6 +27,8 @@ def problem(physics: str, n: int):
         return I.drop(shape=(n, n, n), radius=20.0 * n / 128.0)
     if physics == "single":
         return I.poiseuille(shape=(n, n, n))
+    if physics == "freesurface":
+        return I.penetration(shape=(n, n, n), seed=0)
     raise ValueError(physics)
 
 
@@ -61,7 +63,7 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
     s = sub.add_parser("step")
-    s.add_argument("--physics", default="miscible", choices=["single", "miscible", "immiscible"])
+    s.add_argument("--physics", default="miscible", choices=["single", "miscible", "immiscible", "freesurface"])
     s.add_argument("--size", type=int, default=256)
     s.add_argument("--storage", default="f32", choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s"])
     s.add_argument("--steps", type=int, default=10)

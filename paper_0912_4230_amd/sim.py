@@ -148,6 +148,16 @@ class Simulation:
         B.lbm_populations(self.h, lattice, out.data_ptr())
         return out
 
+    def free_surface(self):
+        """Free surface: (classes uint8 (nz,ny,nx) 0 gas / 1 interface / 2 liquid /
+        3 solid, liquid mass float64 (nz,ny,nx), lost excess mass) on the device."""
+        import torch
+        nx, ny, nz = self.shape
+        cls = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
+        mass = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device)
+        lost = B.lbm_free_surface(self.h, cls.data_ptr(), mass.data_ptr())
+        return cls, mass, lost
+
     def close(self):
         if getattr(self, "h", None) is not None:
             B.lbm_destroy(self.h)

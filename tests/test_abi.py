@@ -144,3 +144,22 @@ def test_maximum_lattice_sizes(storage, nz):
     assert ok > 2 * 19 * nx * ny * nz * {B.LBM_F64: 8, B.LBM_F32: 4}.get(storage, 2)
     d = _desc(nx=nx, ny=ny, nz=nz + 1, storage=storage)
     assert B.lbm_workspace_bytes(d) == 0
+
+
+def test_free_surface_descriptions():
+    """Free surface: its workspace adds the class, mass and fill-fraction
+    planes; reservoir faces are rejected before any GPU call."""
+    from paper_0912_4230_amd import inputs as I
+    from paper_0912_4230_amd.sim import make_desc
+    p = I.slab(shape=(48, 20, 10))
+    q = I.Problem(shape=p.shape).fill_defaults()
+    ws_fs = B.lbm_workspace_bytes(make_desc(p, B.LBM_F32))
+    ws_1 = B.lbm_workspace_bytes(make_desc(q, B.LBM_F32))
+    n = 48 * 20 * 10
+    assert ws_fs - ws_1 >= 3 * n + 7 * 8 * n
+    p.faces[0] = I.Face(kind=I.RESERVOIR)
+    p.faces[1] = I.Face(kind=I.RESERVOIR)
+    assert B.lbm_workspace_bytes(make_desc(p, B.LBM_F32)) == 0
+    # every free-surface generator gives a valid description
+    for g in (I.falling_drop(), I.falling_drop(shape=(12, 10, 9), radius=3.0, axis=2), I.pool(), I.slab()):
+        assert B.lbm_workspace_bytes(make_desc(g, B.LBM_F64)) > 0
