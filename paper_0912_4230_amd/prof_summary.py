@@ -1,10 +1,13 @@
 """Summarise rocprofv3 CSV output into the short text records kept in profiles/.
 
   python -m paper_0912_4230_amd.prof_summary stats <kernel_stats.csv>
+  python -m paper_0912_4230_amd.prof_summary tail <kernel_trace.csv> N
   python -m paper_0912_4230_amd.prof_summary pmc <counter_collection.csv> [<more.csv> ...]
   python -m paper_0912_4230_amd.prof_summary source-sha
 
 `stats` prints the per-kernel table (calls, average / min / max duration);
+`tail` prints the same over the last N dispatches of each kernel of a trace
+(the steady state, without the start-up transient);
 `pmc` prints, per kernel and counter, the per-dispatch values; `source-sha`
 prints the SHA-256 of the kernel sources, which ties a counter record to the
 code it was taken from.
@@ -37,6 +40,16 @@ def stats(path):
               f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}")
 
 
+def tail(path, n):
+    per = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        per[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print(f"{'kernel (last ' + str(n) + ' dispatches)':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}")
+    for k, v in per.items():
+        w = v[-n:]
+        print(f"{k[:70]:70s} {len(w):6d} {sum(w) / len(w):10.1f} {min(w):10.1f} {max(w):10.1f}")
+
+
 def pmc(paths):
     agg = defaultdict(list)
     for p in paths:
@@ -53,6 +66,8 @@ def main():
     what = sys.argv[1]
     if what == "stats":
         stats(sys.argv[2])
+    elif what == "tail":
+        tail(sys.argv[2], int(sys.argv[3]))
     elif what == "pmc":
         pmc(sys.argv[2:])
     elif what == "source-sha":

@@ -89,6 +89,15 @@ def test_porous_3d_drop_with_obstacles_f64():
     _compare(p, [1, 60, 150, 240], diag_every=7, name="3D porous drop with obstacles 14x12x18")
 
 
+def test_ragged_box_f64():
+    """A box whose cell count is not a multiple of the 16-cell tiles of the
+    class passes (13 x 11 x 17 = 2431 cells) nor of the 256-cell blocks."""
+    shape = (13, 11, 17)
+    p = I.falling_drop(shape=shape, radius=3.6, centre=(6.3, 5.4, 10.2), G=5e-4, tau=0.75, axis=2)
+    assert (13 * 11 * 17) % 16 != 0
+    _compare(p, [30, 90, 200], diag_every=13, name="ragged drop 13x11x17")
+
+
 def test_full_tensor_medium_f64():
     shape = (16, 13, 15)
     p = I.falling_drop(shape=shape, radius=4.0, centre=(8.0, 6.5, 9.0), G=4e-4, tau=0.9, axis=2)
