@@ -315,6 +315,28 @@ def freesurface_leg(n, steps, warmup, storages=("f32", "bf16")):
     return out
 
 
+def wood_leg(n, steps, warmup, storages=("f32", "bf16")):
+    """The paper's wood workload in 3D (Sec. 5.5): the spruce medium from the
+    density law, the porosity law and Eq. Ktensor, rings inclined by 45 degrees
+    in the cross-section (full K^-1 tensor per cell), adhesive driven along the
+    grain between reservoirs, the hardening law of Eq. nuall with the paper's
+    constants.  Algorithmic bytes per cell as the inclined-ring leg."""
+    from paper_0912_4230_amd import inputs as I
+    log(f"bench: generating the {n}^3 wood medium")
+    q = I.wood(shape=(n, n, n))
+    ncell = n ** 3
+    out = {"workload": f"wood {n}^3: spruce density law, Eq. Ktensor, rings at 45 deg, flow along the grain"}
+    for st in storages:
+        ms, dg = time_gpu(q, st, steps, warmup)
+        s = ms / steps
+        bpl = storage_bpl(st) + 4 * 4
+        out[st] = {"ms_per_step": round(s, 5), "MLUPS": round(ncell / s / 1e3, 1), "bytes_per_lup": bpl,
+                   "achieved_GBs": round(bpl * ncell / (s / 1e3) / 1e9, 1), "max_v": dg[6],
+                   "nonfinite": int(dg[7])}
+        log(f"bench: wood {st}: {out[st]}")
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -374,6 +396,7 @@ def main():
     ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--no-inclined", action="store_true")
     ap.add_argument("--no-freesurface", action="store_true")
+    ap.add_argument("--no-wood", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle with 1 and all threads on the 32^3 channel and 64^3 x 200 steps")
     ap.add_argument("--precision", action="store_true",
@@ -449,6 +472,8 @@ def main():
         log(f"bench: plain method 32^3 FP64: {out['plain_method_32']}")
     if not args.no_inclined and args.storage == "f32":
         out["inclined_rings"] = inclined_leg(n, min(args.steps, 300), args.warmup)
+    if not args.no_wood and args.storage == "f32":
+        out["wood"] = wood_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_freesurface and args.storage == "f32":
         out["free_surface"] = freesurface_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_serve:

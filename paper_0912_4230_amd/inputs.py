@@ -199,6 +199,73 @@ def inclined_spruce_medium(shape, seed: int = 0, ratio: float = 100.0, angle_deg
     return eps, kinv
 
 
+# Spruce wood of Sec. 5.5 (wood-properties paragraph): density law of Eq.
+# wooddensityfunc with rho_0 = 310 kg/m^3, a = 24/Delta, b = 0.8, c = 9.6/Delta,
+# ring width Delta = 2.9 mm (positions in mm); permeabilities of Eq. Ktensor in
+# mm^2 along the radial, longitudinal and tangential axes.  The cell-wall density
+# rho_max is not printed: 1500 kg/m^3, the usual value for the wood substance.
+SPRUCE_RHO0 = 310.0
+SPRUCE_RING_MM = 2.9
+SPRUCE_B = 0.8
+SPRUCE_A = 24.0 / SPRUCE_RING_MM
+SPRUCE_C = 9.6 / SPRUCE_RING_MM
+WOOD_RHO_MAX = 1500.0
+WOOD_K_MM2 = (8.2e-10, 51470e-10, 0.82e-10)   # radial, longitudinal, tangential
+
+
+def wood_density(s_mm):
+    """Eq. wooddensityfunc made periodic over the year rings: rho(s) = rho_0
+    [1 + 2 a x^b exp(-c x)] with x = s mod Delta, the position in the ring (mm)."""
+    x = np.mod(np.asarray(s_mm, dtype=np.float64), SPRUCE_RING_MM)
+    return SPRUCE_RHO0 * (1.0 + 2.0 * SPRUCE_A * x ** SPRUCE_B * np.exp(-SPRUCE_C * x))
+
+
+def wood_medium(shape, angle_deg: float = 45.0, ring_cells: float = 30.0, rho_max: float = WOOD_RHO_MAX,
+                origin=(0, 0, 0)):
+    """The spruce medium of Sec. 5.5 built from the paper's laws: the x-y plane is
+    the wood cross-section (radial-tangential), the year rings inclined by
+    `angle_deg` in it (radial axis n = (cos a, sin a, 0), tangential
+    t = (-sin a, cos a, 0)), z the longitudinal (grain) axis; one ring is
+    `ring_cells` cells wide (the ring distance of the penetration example), so a
+    cell is Delta / ring_cells mm.  Per cell, at the ring coordinate
+    s = n.(x, y, z) Delta / ring_cells: rho(s) by Eq. wooddensityfunc,
+    eps = 1 - rho / rho_max (Eq. epsilonfunction), and the permeabilities of Eq.
+    Ktensor, K_k = (rho_max / rho)^2 eps^(11/3) K_k^0 / dx^2 in lattice units, so
+    K^-1 = n n^T / K_r + t t^T / K_t + z z^T / K_L.  Returns (eps (nz,ny,nx),
+    kinv (6,nz,ny,nx) = {xx, yy, zz, xy, xz, yz}) in float64; crops agree with the
+    full medium through `origin`."""
+    nx, ny, nz = shape
+    ox, oy, oz = origin
+    a = math.radians(angle_deg)
+    c, sn = math.cos(a), math.sin(a)
+    Z, Y, X = np.meshgrid(np.arange(nz, dtype=np.int64) + oz, np.arange(ny, dtype=np.int64) + oy,
+                          np.arange(nx, dtype=np.int64) + ox, indexing="ij")
+    dx_mm = SPRUCE_RING_MM / ring_cells
+    rho = wood_density((c * X + sn * Y) * dx_mm)
+    eps = 1.0 - rho / rho_max
+    pref = (rho_max / rho) ** 2 * eps ** (11.0 / 3.0) / (dx_mm * dx_mm)
+    ikr = 1.0 / (pref * WOOD_K_MM2[0])
+    ikl = 1.0 / (pref * WOOD_K_MM2[1])
+    ikt = 1.0 / (pref * WOOD_K_MM2[2])
+    kinv = np.empty((6, nz, ny, nx))
+    kinv[0] = ikr * (c * c) + ikt * (sn * sn)
+    kinv[1] = ikr * (sn * sn) + ikt * (c * c)
+    kinv[2] = ikl
+    kinv[3] = (ikr - ikt) * (c * sn)
+    kinv[4] = 0.0
+    kinv[5] = 0.0
+    return eps, kinv
+
+
+def wood_hardening_law(p: "Problem", alpha: float = 2e-3) -> "Problem":
+    """Eq. nuall with the urea-formaldehyde constants of Sec. 5.5: nu_g = 0.15,
+    a = 2.05e-9, beta = 1e-3; alpha is not printed: 2e-3 per step, so that the
+    reaction term a exp(alpha t) reaches 1 (the viscosity doubles) after 1e4 steps."""
+    beta = 1e-3
+    p.nu0, p.a0, p.a1, p.alpha, p.cap, p.k1, p.k0 = 0.15, 1.0, 2.05e-9, alpha, 1e30, -beta, beta
+    return p
+
+
 # --------------------------------------------------------------------------
 # problems shaped like the paper's workloads
 
@@ -252,6 +319,22 @@ def miscible(shape=(256, 256, 256), seed=0, ratio=100.0, origin=(0, 0, 0), D=0.0
     p = Problem(shape=tuple(shape), physics=MISCIBLE, forchheimer=True, tau_d=0.5 + 3.0 * D,
                 faces=faces, eps=eps, kinv=kinv)
     hardening_law(p)
+    return p.fill_defaults()
+
+
+def wood(shape=(256, 256, 256), angle_deg=45.0, D=0.05, p_ext=P_EXT, origin=(0, 0, 0)) -> Problem:
+    """Miscible adhesive in the spruce medium of Sec. 5.5 (`wood_medium`, rings
+    inclined by 45 degrees in the cross-section), driven along the grain: inlet
+    reservoir at z = 0 with rho = 1 + 3 p_ext and C = 1, outlet at z = nz-1 with
+    rho = 1 and C = 0, periodic in x and y; the hardening law of Eq. nuall with
+    the paper's constants (`wood_hardening_law`), Darcy + Forchheimer drag."""
+    eps, kinv = wood_medium(shape, angle_deg=angle_deg, origin=origin)
+    faces = [Face() for _ in range(6)]
+    faces[4] = Face(kind=RESERVOIR, rho=1.0 + 3.0 * p_ext, conc=1.0)
+    faces[5] = Face(kind=RESERVOIR, rho=1.0, conc=0.0)
+    p = Problem(shape=tuple(shape), physics=MISCIBLE, forchheimer=True, tau_d=0.5 + 3.0 * D,
+                faces=faces, eps=eps, kinv=kinv)
+    wood_hardening_law(p)
     return p.fill_defaults()
 
 

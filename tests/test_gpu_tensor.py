@@ -76,6 +76,20 @@ def test_inclined_rings_miscible_ragged(storage, tol):
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_paper_wood_medium_ragged(storage, tol):
+    """The spruce medium of Sec. 5.5 from the paper's laws (density law,
+    porosity, Eq. Ktensor with 45-degree rings; K^-1 up to 2.5e9), adhesive
+    driven along the grain between reservoirs, the hardening law of Eq. nuall
+    with the paper's constants; ragged grid."""
+    p = I.wood(shape=(37, 29, 23), origin=(5, 3, 0))
+    g, r, mask, dg, od = run_pair(p, 120, storage, chunks=[50, 70])
+    e = errors(g, r, mask)
+    report(f"paper wood medium 37x29x23 x120 {storage}", e)
+    assert e["rho"] < tol and e["conc"] < tol
+    assert e["vel"] < (tol if storage == "f64" else 1e-3)
+
+
 def test_inclined_rings_two_fluid_with_obstacles():
     """A drop in the inclined medium among obstacles: full tensor, obstacle
     mask and the two-fluid model together (FP64)."""
