@@ -42,6 +42,9 @@
  *  - two-fluid (immiscible) mode: second lattice g = fluid-1 populations,
  *    colour field rho_1 = Sum g, C = rho_1 / rho, nu = C nu_1 + (1-C) nu_2,
  *    recolouring g~_i = C f~_i + beta C (1-C) rho w_i cos(v_i, F);
+ *  - several solutes (miscible mode): each its own lattice, tau_d and
+ *    reservoir concentrations, all advected by V'; the viscosity law reads
+ *    the first solute's concentration;
  *  - free-surface mode (Sec. 3): liquid, interface and gas cells, mass
  *    exchange, reconstruction from gas cells and class conversion, with the
  *    readings stated beside fs_step below;
@@ -122,7 +125,11 @@ typedef struct {
     double face_rho[6], face_conc[6], face_angle[6];  /* reservoir rho, C; wall angle (deg) */
     double solid_angle; /* contact angle (deg) of the obstacle cells of a solid mask */
     int full_tensor;    /* 1: K^-1 is a full symmetric tensor, 6 planes {xx,yy,zz,xy,xz,yz} */
+    int nspecies;       /* miscible: number of solutes (0 or 1: one; at most ORC_MAXSP) */
+    double tau_dx[3];   /* relaxation times of solutes 2.. */
+    double face_concx[3][6];  /* reservoir concentrations of solutes 2.. */
 } orc_params;
+#define ORC_MAXSP 4
 
 typedef struct {
     orc_params p;
@@ -139,6 +146,9 @@ typedef struct {
     unsigned char *fst;       /* free surface: FS_GAS / FS_IF / FS_LIQ per non-solid cell */
     double *mass, *lam;       /* free surface: liquid mass m and fill fraction lambda = m / rho */
     double fs_lost;           /* free surface: excess mass without an interface neighbour */
+    int nsx;                  /* miscible: number of solutes beyond the first */
+    double *hx[2];            /* their populations, [k][q][idx], copies like h */
+    double *concx;            /* their concentrations of the last step, [k][idx] */
     long step;                /* number of completed steps */
 } orc_state;
 
@@ -587,6 +597,34 @@ static void collide_cell(const orc_state *s, int x, int y, int z, double t,
     mom[4] = C;
 }
 
+/* Solutes beyond the first (the extension to several species that Sec. 2.2
+ * prepares): each has its own lattice, relaxation time tau_d,k and reservoir
+ * concentrations, and follows Eqs. equild and boltzeqD with the velocity V'
+ * of the hydrodynamic lattice, exactly as the first solute; the viscosity
+ * law reads the first solute's concentration.  From the streamed hin of
+ * solute k (k >= 1) at a fluid cell: hout and C_k.                         */
+static double solute_extra(const orc_state *s, int x, int y, int z, int k, const double Vp[3],
+                           const double hin[NQ], double hout[NQ])
+{
+    const orc_params *p = &s->p;
+    long i0 = cidx(s, x, y, z);
+    double eps = s->eps[i0];
+    double sh = 0.0;
+    for (int q = 0; q < NQ; ++q) sh += hin[q];
+    double C = sh / eps;
+    double tau_d = p->tau_dx[k - 1];
+    double D = (tau_d - 0.5) / 3.0, vs[3] = {Vp[0], Vp[1], Vp[2]};
+    if (p->eps_grad) {
+        double g[3];
+        eps_gradient(s, x, y, z, g);
+        for (int a = 0; a < 3; ++a) vs[a] += D * g[a];
+    }
+    double he[NQ];
+    heq(eps * C, vs, he);
+    for (int q = 0; q < NQ; ++q) hout[q] = hin[q] - (hin[q] - he[q]) / tau_d;
+    return C;
+}
+
 /* fixed state of a reservoir cell: the equilibrium of (rho_bc, V' = 0, F = 0);
  * solute h = w eps C_bc; fluid-1 populations g = C_bc w rho_bc.            */
 static void reservoir_state(const orc_state *s, long i, double fo[NQ], double ho[NQ], double mom[5])
@@ -696,6 +734,7 @@ void orc_destroy(orc_state *s)
     free(s->f[0]); free(s->f[1]); free(s->h[0]); free(s->h[1]);
     free(s->rho); free(s->vel); free(s->conc); free(s->vsnap); free(s->rho1);
     free(s->fst); free(s->mass); free(s->lam);
+    free(s->hx[0]); free(s->hx[1]); free(s->concx);
     free(s);
 }
 
@@ -975,6 +1014,7 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
                       const unsigned char *solid)
 {
     lattice_setup();
+    if (p->nspecies < 0 || p->nspecies > ORC_MAXSP || (p->nspecies > 1 && p->physics != PHYS_MISCIBLE)) return NULL;
     if (p->physics == PHYS_FREESURF)
         for (int f = 0; f < 6; ++f)
             if (p->face_kind[f] == FACE_RESERVOIR) return NULL;
@@ -998,6 +1038,13 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
     s->rho1 = calloc(n, sizeof(double));
     if (!s->eps || !s->kinv || (p->full_tensor && !s->ksqrt) || !s->type || !s->tface || !s->f[0] || !s->h[0] || !s->rho ||
         !s->vel || !s->conc || !s->vsnap || !s->rho1) { orc_destroy(s); return NULL; }
+    s->nsx = (p->physics == PHYS_MISCIBLE && p->nspecies > 1) ? p->nspecies - 1 : 0;
+    if (s->nsx) {
+        s->hx[0] = calloc((size_t)s->nsx * NQ * n, sizeof(double));
+        s->hx[1] = calloc((size_t)s->nsx * NQ * n, sizeof(double));
+        s->concx = calloc((size_t)s->nsx * n, sizeof(double));
+        if (!s->hx[0] || !s->hx[1] || !s->concx) { orc_destroy(s); return NULL; }
+    }
     memcpy(s->eps, eps, sizeof(double) * n);
     memcpy(s->kinv, kinv, sizeof(double) * nk * n);
     if (p->full_tensor) {
@@ -1059,6 +1106,36 @@ orc_state *orc_create(const orc_params *p, const double *eps, const double *kinv
                     s->h[0][(long)q * n + i] = ho[q];
                 }
             }
+    /* solutes beyond the first: h = h^eq(eps C0_k, V0 + D_k grad(eps)/eps), c0
+     * holding one plane per solute; reservoir cells w eps C_bc,k */
+    for (int k = 1; k <= s->nsx; ++k) {
+        double *H = s->hx[0] + (size_t)(k - 1) * NQ * n;
+        double D = (p->tau_dx[k - 1] - 0.5) / 3.0;
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long i = cidx(s, x, y, z);
+                    double ho[NQ], C = 0.0;
+                    if (s->type[i] == CELL_SOLID) continue;
+                    if (s->type[i] == CELL_RESERVOIR) {
+                        C = p->face_concx[k - 1][s->tface[i]];
+                        for (int q = 0; q < NQ; ++q) ho[q] = WGT[q] * s->eps[i] * C;
+                    } else {
+                        double vs[3] = {vel0[i], vel0[n + i], vel0[2 * n + i]};
+                        C = c0[(size_t)k * n + i];
+                        if (p->eps_grad) {
+                            double g[3];
+                            eps_gradient(s, x, y, z, g);
+                            for (int a = 0; a < 3; ++a) vs[a] += D * g[a];
+                        }
+                        heq(eps[i] * C, vs, ho);
+                    }
+                    for (int q = 0; q < NQ; ++q) H[(long)q * n + i] = ho[q];
+                    s->concx[(size_t)(k - 1) * n + i] = C;
+                }
+    }
+    if (s->nsx) memcpy(s->hx[1], s->hx[0], sizeof(double) * (size_t)s->nsx * NQ * n);
     if (p->physics == PHYS_FREESURF && fs_init(s, c0, rho0) != 0) { orc_destroy(s); return NULL; }
     memcpy(s->vsnap, s->vel, sizeof(double) * 3 * n);
     s->step = 0;
@@ -1108,6 +1185,20 @@ int orc_step(orc_state *s, int nsteps)
                     for (int q = 0; q < NQ; ++q) {
                         Fn[(long)q * n + i] = fo[q];
                         Hn[(long)q * n + i] = ho[q];
+                    }
+                    for (int k = 1; k <= s->nsx; ++k) {
+                        const double *Xc = s->hx[s->cur] + (size_t)(k - 1) * NQ * n;
+                        double *Xn = s->hx[1 - s->cur] + (size_t)(k - 1) * NQ * n;
+                        double xin[NQ], xo[NQ], C;
+                        if (s->type[i] == CELL_RESERVOIR) {
+                            C = s->p.face_concx[k - 1][s->tface[i]];
+                            for (int q = 0; q < NQ; ++q) xo[q] = WGT[q] * s->eps[i] * C;
+                        } else {
+                            for (int q = 0; q < NQ; ++q) xin[q] = pull(s, Xc, x, y, z, q);
+                            C = solute_extra(s, x, y, z, k, mom + 1, xin, xo);
+                        }
+                        for (int q = 0; q < NQ; ++q) Xn[(long)q * n + i] = xo[q];
+                        s->concx[(size_t)(k - 1) * n + i] = C;
                     }
                     s->rho[i] = mom[0];
                     s->vel[i] = mom[1];
@@ -1170,9 +1261,14 @@ void orc_diag(orc_state *s, double out[8])
 }
 
 /* current post-collision populations of lattice L (0: f as deviations
- * f - w, 1: h or g), 19 planes in this file's direction order.            */
+ * f - w, 1: h or g, 2..: the further solutes), 19 planes in this file's
+ * direction order.                                                         */
 void orc_get_state(const orc_state *s, int L, double *out)
 {
+    if (L >= 2) {
+        memcpy(out, s->hx[s->cur] + (size_t)(L - 2) * NQ * s->n, sizeof(double) * NQ * s->n);
+        return;
+    }
     memcpy(out, L == 0 ? s->f[s->cur] : s->h[s->cur], sizeof(double) * NQ * s->n);
 }
 
@@ -1222,6 +1318,30 @@ void orc_step_cells(orc_state *s, long ncells, const long *cells, double *fo_out
 
 /* cell classes (0 fluid, 1 solid, 2 reservoir) */
 void orc_cell_types(const orc_state *s, unsigned char *out) { memcpy(out, s->type, s->n); }
+
+/* concentration of solute k (0: the first) of the last step into out (ncell). */
+int orc_species_conc(const orc_state *s, int k, double *out)
+{
+    if (k == 0) { memcpy(out, s->conc, sizeof(double) * s->n); return 0; }
+    if (k < 0 || k > s->nsx) return -1;
+    memcpy(out, s->concx + (size_t)(k - 1) * s->n, sizeof(double) * s->n);
+    return 0;
+}
+
+/* Sum over fluid cells of eps C_k for every solute k (the conserved solute
+ * masses of Eq. diffusionporous), into out[nspecies]. */
+int orc_species_totals(const orc_state *s, double *out)
+{
+    int ns = 1 + s->nsx;
+    for (int k = 0; k < ns; ++k) {
+        const double *C = k == 0 ? s->conc : s->concx + (size_t)(k - 1) * s->n;
+        double acc = 0.0;
+        for (long i = 0; i < s->n; ++i)
+            if (s->type[i] == CELL_FLUID) acc += s->eps[i] * C[i];
+        out[k] = acc;
+    }
+    return ns;
+}
 
 /* free surface: per cell class (0 gas, 1 interface, 2 liquid; solid cells 0)
  * and liquid mass m; the total excess mass that found no interface cell to

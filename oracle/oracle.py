@@ -32,6 +32,9 @@ class OrcParams(C.Structure):
         ("face_rho", C.c_double * 6), ("face_conc", C.c_double * 6), ("face_angle", C.c_double * 6),
         ("solid_angle", C.c_double),
         ("full_tensor", C.c_int),
+        ("nspecies", C.c_int),
+        ("tau_dx", C.c_double * 3),
+        ("face_concx", (C.c_double * 6) * 3),
     ]
 
 
@@ -70,6 +73,10 @@ def lib():
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_fs_state.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte), dp]
         L.orc_fs_state.restype = C.c_double
+        L.orc_species_conc.argtypes = [C.c_void_p, C.c_int, dp]
+        L.orc_species_conc.restype = C.c_int
+        L.orc_species_totals.argtypes = [C.c_void_p, dp]
+        L.orc_species_totals.restype = C.c_int
         _lib = L
     return _lib
 
@@ -100,6 +107,11 @@ def params_from_problem(p) -> OrcParams:
     o.face_angle = (C.c_double * 6)(*[float(f.angle) for f in p.faces])
     o.solid_angle = float(p.solid_angle)
     o.full_tensor = int(p.kinv is not None and np.asarray(p.kinv).shape[0] == 6)
+    o.nspecies = int(p.nspecies)
+    for k, t in enumerate(p.species_tau_d):
+        o.tau_dx[k] = float(t)
+        for f in range(6):
+            o.face_concx[k][f] = float(p.faces[f].conc_x[k]) if len(p.faces[f].conc_x) > k else 0.0
     return o
 
 
@@ -234,6 +246,20 @@ class Oracle:
         lost = lib().orc_fs_state(self.h, cls, _dp(m))
         return (np.frombuffer(cls, dtype=np.uint8).copy().reshape(nz, ny, nx),
                 m.reshape(nz, ny, nx), lost)
+
+    def species_conc(self, k: int):
+        """Concentration of solute k (0: the first) of the last step, (nz,ny,nx)."""
+        nx, ny, nz = self.shape
+        out = np.zeros(self.n)
+        if lib().orc_species_conc(self.h, int(k), _dp(out)) != 0:
+            raise IndexError(k)
+        return out.reshape(nz, ny, nx)
+
+    def species_totals(self):
+        """Sum over fluid cells of eps C_k for every solute."""
+        out = np.zeros(4)
+        ns = lib().orc_species_totals(self.h, _dp(out))
+        return out[:ns]
 
     def get_state(self, lattice_id: int):
         out = np.zeros(NQ * self.n)

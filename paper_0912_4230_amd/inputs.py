@@ -32,6 +32,7 @@ class Face:
     rho: float = 1.0        # reservoir density
     conc: float = 0.0       # reservoir concentration
     angle: float = 90.0     # wall contact angle in degrees (two-fluid model)
+    conc_x: Tuple[float, ...] = ()   # reservoir concentrations of solutes 2, 3, ...
 
 
 @dataclasses.dataclass
@@ -64,6 +65,8 @@ class Problem:
     c0: Optional[np.ndarray] = None     # (nz,ny,nx); free surface: initial fill fraction
     solid: Optional[np.ndarray] = None  # (nz,ny,nx) nonzero = obstacle cell (no state, bounce-back)
     solid_angle: float = 90.0           # contact angle of the obstacle surfaces (two-fluid model)
+    species_tau_d: Tuple[float, ...] = ()   # miscible: relaxation times of solutes 2, 3, ... (c0 then
+                                            # holds one plane per solute: (nspecies, nz, ny, nx))
 
     @property
     def ncell(self) -> int:
@@ -81,13 +84,17 @@ class Problem:
         if self.vel0 is None:
             self.vel0 = np.zeros((3, nz, ny, nx))
         if self.c0 is None:
-            self.c0 = np.zeros((nz, ny, nx))
+            self.c0 = np.zeros((nz, ny, nx)) if self.nspecies == 1 else np.zeros((self.nspecies, nz, ny, nx))
         return self
 
     def uniform_medium(self) -> bool:
         e = self.eps
         k = self.kinv
         return bool(np.all(e == e.flat[0]) and all(np.all(k[a] == k[a].flat[0]) for a in range(k.shape[0])))
+
+    @property
+    def nspecies(self) -> int:
+        return 1 + len(self.species_tau_d)
 
     @property
     def full_tensor(self) -> bool:
