@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -337,6 +339,29 @@ def wood_leg(n, steps, warmup, storages=("f32", "bf16")):
     return out
 
 
+def species_leg(n, steps, warmup, storages=("f32", "bf16")):
+    """The miscible workload with a second solute (its own lattice, tau_d 0.8,
+    inlet concentration 0.5) sharing V' with the first: algorithmic bytes per
+    cell = the miscible step's + one more lattice read and written."""
+    from paper_0912_4230_amd import inputs as I
+    q = I.miscible(shape=(n, n, n), seed=0)
+    q.species_tau_d = (0.8,)
+    q.faces[0].conc_x = (0.5,)
+    q.faces[1].conc_x = (0.0,)
+    q.c0 = np.zeros((2, n, n, n))
+    ncell = n ** 3
+    out = {"workload": f"miscible {n}^3 with 2 solutes (tau_d 0.65 and 0.8)"}
+    for st in storages:
+        ms, dg = time_gpu(q, st, steps, warmup)
+        s = ms / steps
+        sb = 4 if st == "f32" else 2
+        bpl = storage_bpl(st) + 2 * 19 * sb
+        out[st] = {"ms_per_step": round(s, 5), "MLUPS": round(ncell / s / 1e3, 1), "bytes_per_lup": bpl,
+                   "achieved_GBs": round(bpl * ncell / (s / 1e3) / 1e9, 1), "nonfinite": int(dg[7])}
+        log(f"bench: two solutes {st}: {out[st]}")
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """FP64 oracle on the host: miscible physics on a 64^3 crop of the same
     seeded medium, as many steps as fit in about budget_s seconds."""
@@ -397,6 +422,7 @@ def main():
     ap.add_argument("--no-inclined", action="store_true")
     ap.add_argument("--no-freesurface", action="store_true")
     ap.add_argument("--no-wood", action="store_true")
+    ap.add_argument("--no-species", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle with 1 and all threads on the 32^3 channel and 64^3 x 200 steps")
     ap.add_argument("--precision", action="store_true",
@@ -472,6 +498,8 @@ def main():
         log(f"bench: plain method 32^3 FP64: {out['plain_method_32']}")
     if not args.no_inclined and args.storage == "f32":
         out["inclined_rings"] = inclined_leg(n, min(args.steps, 300), args.warmup)
+    if not args.no_species and args.storage == "f32":
+        out["two_solutes"] = species_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_wood and args.storage == "f32":
         out["wood"] = wood_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_freesurface and args.storage == "f32":

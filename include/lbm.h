@@ -103,6 +103,8 @@ typedef enum {
  * conversion decisions are taken in double precision on masses kept in
  * double precision in every storage mode. */
 
+#define LBM_MAX_SPECIES 4
+
 typedef enum {
     LBM_F64 = 0,         /* populations and fields in double */
     LBM_F32 = 1,         /* populations and fields in float */
@@ -162,7 +164,20 @@ typedef struct {
     int full_tensor;            /* 1: lbm_medium.kinv holds a full symmetric K^-1 per cell
                                    (the rotated tensor of Eq. Ktensor), 6 planes
                                    {xx, yy, zz, xy, xz, yz}; 0: the diagonal, 3 planes */
+    int nspecies;               /* miscible: number of solutes, 1 to LBM_MAX_SPECIES
+                                   (0 means 1); each further solute has its own lattice */
+    double tau_d_x[LBM_MAX_SPECIES - 1];       /* relaxation times of solutes 2.. */
+    double face_conc_x[LBM_MAX_SPECIES - 1][6]; /* RESERVOIR faces: concentrations of
+                                   solutes 2.., in the face order of face[] */
 } lbm_desc;
+/* Several solutes (the extension to "various species" that Sec. 2.2 prepares):
+ * solute k has its own D3Q19 lattice, relaxation time (D_k = (tau_d,k - 1/2)/3)
+ * and reservoir concentrations, and follows Eqs. equild and boltzeqD with the
+ * shared corrected velocity V' and its own drift D_k grad(eps)/eps.  The
+ * viscosity law reads the first solute's concentration.  lbm_medium.c0 then
+ * holds nspecies planes (solute-major), lbm_moments writes nspecies
+ * concentration planes, lbm_populations takes lattice 1..nspecies for the
+ * solutes, and lbm_solute_totals reduces every solute's mass. */
 
 /* Medium and initial fields (flowchart of Sec. 4: set rho, V, C, the
  * porosity and the permeability).  Device pointers of the real type; NULL
@@ -240,9 +255,16 @@ lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n);
 lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8]);
 
 /* Current post-collision populations of lattice 0 (hydrodynamic, as
- * deviations f_i - w_i) or 1 (second lattice, as is), decoded to the real
- * type: 19 planes in the direction order of lbm_lattice(). */
+ * deviations f_i - w_i) or 1 (second lattice, as is; with several solutes
+ * 1..nspecies are the solutes), decoded to the real type: 19 planes in the
+ * direction order of lbm_lattice(). */
 lbm_status lbm_populations(lbm_t h, int lattice, void *dst);
+
+/* Miscible mode: the mass of every solute over the fluid cells of the last
+ * step, Sum eps C_k (Eq. diffusionporous), in FP64 with a fixed summation
+ * order, into the host array totals[nspecies].  LBM_EINVAL for another
+ * physics.  Synchronises the stream. */
+lbm_status lbm_solute_totals(lbm_t h, double *totals);
 
 /* Free surface (Sec. 3): the cell classes after the last step (ncell bytes:
  * 0 gas, 1 interface, 2 liquid, 3 solid) and the liquid mass per cell

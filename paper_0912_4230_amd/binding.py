@@ -16,11 +16,12 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = range(6
 LBM_SINGLE, LBM_MISCIBLE, LBM_IMMISCIBLE, LBM_FREESURF = range(4)
 LBM_F64, LBM_F32, LBM_BF16_DEV, LBM_F16_DEV, LBM_BF16_SPLIT, LBM_F16_SPLIT = range(6)
 LBM_FACE_PERIODIC, LBM_FACE_WALL, LBM_FACE_RESERVOIR = range(3)
+LBM_MAX_SPECIES = 4
 
 STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV,
                  "bf16s": LBM_BF16_SPLIT, "f16s": LBM_F16_SPLIT}
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_medium", "lbm_step", "lbm_step_batch",
-            "lbm_moments", "lbm_populations", "lbm_free_surface", "lbm_steps_done", "lbm_destroy",
+            "lbm_moments", "lbm_populations", "lbm_solute_totals", "lbm_free_surface", "lbm_steps_done", "lbm_destroy",
             "lbm_lattice", "lbm_strerror"]
 
 
@@ -44,6 +45,9 @@ class lbm_desc(C.Structure):
         ("solid_mask", C.c_int),
         ("solid_contact_angle_deg", C.c_double),
         ("full_tensor", C.c_int),
+        ("nspecies", C.c_int),
+        ("tau_d_x", C.c_double * (LBM_MAX_SPECIES - 1)),
+        ("face_conc_x", (C.c_double * 6) * (LBM_MAX_SPECIES - 1)),
     ]
 
 
@@ -90,6 +94,8 @@ def lib():
         L.lbm_destroy.argtypes = [vp]
         L.lbm_lattice.restype = None
         L.lbm_lattice.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.lbm_solute_totals.restype = C.c_int
+        L.lbm_solute_totals.argtypes = [vp, C.POINTER(C.c_double)]
         L.lbm_free_surface.restype = C.c_int
         L.lbm_free_surface.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
         L.lbm_strerror.restype = C.c_char_p
@@ -142,6 +148,13 @@ def lbm_moments(h, rho_ptr: int = 0, vel_ptr: int = 0, conc_ptr: int = 0, diag=N
 
 def lbm_populations(h, lattice: int, dst_ptr: int) -> int:
     return _check(lib().lbm_populations(h, int(lattice), C.c_void_p(dst_ptr)), "lbm_populations")
+
+
+def lbm_solute_totals(h, nspecies: int):
+    """Sum eps C_k over fluid cells for every solute (list of nspecies floats)."""
+    out = (C.c_double * LBM_MAX_SPECIES)()
+    _check(lib().lbm_solute_totals(h, out), "lbm_solute_totals")
+    return [float(out[k]) for k in range(nspecies)]
 
 
 def lbm_free_surface(h, cls_ptr: int = 0, mass_ptr: int = 0) -> float:

@@ -76,11 +76,29 @@ struct LatDev {
     void *eps, *kinv, *mom, *rho1;
     const void *links;          // obstacle mask as link words (bit 0: solid, bit q: x - v_q solid), or null
     const void *fs;             // free-surface state (FsDev), or null
+    const void *ms;             // further solutes (MsDev), or null
     double *partials, *diag;
     int *err;
     uint32_t div_nx[3], div_nxy[3];   // magic numbers of the divisions by nx and nx*ny
     uint32_t pstride;           // elements from one population plane to the next (>= ncell)
 };
+
+// Solutes beyond the first (miscible mode with several species), in the
+// workspace: per solute its two population copies (19 planes of the lattice's
+// plane stride) and, for split storage, its two mass planes; its D and tau_d
+// (D = (tau_d - 1/2)/3 in double, as for the first solute) and reservoir
+// concentrations.  The moments buffer then holds their concentrations as
+// planes 5, 6, ...
+constexpr int MAXSPX = 3;
+struct MsDev {
+    int nsx;                    // number of further solutes (1..MAXSPX)
+    void *h[MAXSPX][2];
+    void *hm[MAXSPX][2];
+    double tau_d[MAXSPX], D[MAXSPX];
+    double face_conc[MAXSPX][6];
+};
+
+__device__ inline const MsDev *ms_of(const LatDev *L) { return static_cast<const MsDev *>(L->ms); }
 
 // Arguments of one batched launch: lattice l owns logical blocks
 // [blk_start[l], blk_start[l+1]).  flags bit 0: copy holding step n; bit 1:
@@ -732,8 +750,10 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 // ---------------------------------------------------------------------------
 // The step kernel: pull-stream both lattices, moments, viscosity, porous
 // force, (colour gradient), collide, write the other copy.  FT: every lattice
-// of the launch has a full permeability tensor (eigenframe form).
-template <int PHYS, class S, bool FT = false>
+// of the launch has a full permeability tensor (eigenframe form).  MS
+// (miscible): the lattices may carry further solutes, updated after the
+// first with the same V' (a runtime count per lattice, possibly 0).
+template <int PHYS, class S, bool FT = false, bool MS = false>
 __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
@@ -772,6 +792,9 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
     // measured up to 30% slower (narrow rows) than the extra bytes.
     R d[NQ], hq[NQ];
     const int dst = src ^ 1;
+    // what the further solutes take from the fluid branch
+    [[maybe_unused]] Nbr bx{};
+    [[maybe_unused]] R x_eps = 1, x_ie = 1, x_u[3] = {0, 0, 0}, x_g[3] = {0, 0, 0};
     if (type == CELL_FLUID) {
         const Nbr b = neighbours(L, x, y, z, lw);
         pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
@@ -848,6 +871,17 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
                 vs[0] += k * gx;
                 vs[1] += k * gy;
                 vs[2] += k * gz;
+                if constexpr (MS) {
+                    x_g[0] = gx;
+                    x_g[1] = gy;
+                    x_g[2] = gz;
+                }
+            }
+            if constexpr (MS) {
+                bx = b;
+                x_eps = eps;
+                x_ie = ie;
+                for (int c = 0; c < 3; ++c) x_u[c] = u[c];
             }
             const R omd = R(1) / R(L->tau_d);
             const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
@@ -882,6 +916,7 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
         const R rb = R(L->face_rho[face]), cb = R(L->face_conc[face]);
         R eps = R(1);
         if constexpr (PHYS == PH_MISCIBLE) eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
+        if constexpr (MS) x_eps = eps;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const R w = weight<R>(q);
@@ -896,6 +931,36 @@ __global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
     if (idx < ncell && __builtin_amdgcn_ballot_w64(type != CELL_SOLID) != 0) {
         if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[dst], L->hm[dst], L->pstride, idx, hq);
         store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
+    }
+    if constexpr (MS) {
+        // further solutes: the first solute's update with their own D, tau_d
+        // and reservoir concentrations, one at a time
+        const MsDev *X = ms_of(L);
+        const int nsx = X ? X->nsx : 0;
+        for (int k = 0; k < nsx; ++k) {
+            R hk[NQ];
+            if (type == CELL_FLUID) {
+                pull_all<S>(X->h[k][src], X->hm[k][src], L->pstride, idx, bx, hk);
+                R sh = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) sh += hk[q];
+                const R kk = R(3) * R(X->D[k]) * x_ie;
+                const R vs[3] = {x_u[0] + kk * x_g[0], x_u[1] + kk * x_g[1], x_u[2] + kk * x_g[2]};
+                const R omd = R(1) / R(X->tau_d[k]);
+                const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
+                collide_h<R>(hk, R(1) - omd, H, vs);
+                if (mom) stp<R>(L->mom, ncell, 5 + k, idx, sh * x_ie);
+            } else if (type == CELL_RES) {
+                const R cb = R(X->face_conc[k][face]);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) hk[q] = weight<R>(q) * x_eps * cb;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) hk[q] = R(0);
+            }
+            if (idx < ncell && __builtin_amdgcn_ballot_w64(type != CELL_SOLID) != 0)
+                store_all<S>(X->h[k][dst], X->hm[k][dst], L->pstride, idx, hk);
+        }
     }
     if (mom) {
         double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1245,6 +1310,40 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
     stp<R>(M, ncell, 2, idx, mu[1]);
     stp<R>(M, ncell, 3, idx, mu[2]);
     stp<R>(M, ncell, 4, idx, mC);
+    if constexpr (PHYS == PH_MISCIBLE) {
+        // further solutes: h = h^eq(eps C0_k, V0 + D_k grad(eps)/eps) from
+        // plane k of c0, as the first solute; reservoirs w eps C_bc,k
+        const MsDev *X = ms_of(L);
+        const int nsx = X ? X->nsx : 0;
+        for (int k = 0; k < nsx; ++k) {
+            R hk[NQ], Ck = 0;
+            if (type == CELL_SOLID) {
+                for (int q = 0; q < NQ; ++q) hk[q] = R(0);
+            } else if (type == CELL_RES) {
+                Ck = R(X->face_conc[k][face]);
+                for (int q = 0; q < NQ; ++q) hk[q] = weight<R>(q) * eps * Ck;
+            } else {
+                Ck = ia.c0 ? ia.c0[size_t(k + 1) * n + idx] : R(0);
+                if (bad(Ck)) *L->err = 1;
+                R vs[3] = {u0[0], u0[1], u0[2]};
+                if (L->eps_grad && !L->uniform_eps) {
+                    const Nbr b = neighbours(L, x, y, z, lw);
+                    R gx = 0, gy = 0, gz = 0;
+                    eps_grad_acc<R>(L->eps, b, eps, gx, gy, gz);
+                    const R kk = R(3) * R(X->D[k]) / eps;
+                    vs[0] += kk * gx;
+                    vs[1] += kk * gy;
+                    vs[2] += kk * gz;
+                }
+                for (int q = 0; q < NQ; ++q) hk[q] = R(0);
+                const R ec = eps * Ck;
+                const R H[3] = {weight<R>(0) * ec, weight<R>(1) * ec, weight<R>(7) * ec};
+                collide_h<R>(hk, R(0), H, vs);
+            }
+            for (int cpy = 0; cpy < 2; ++cpy) store_all<S>(X->h[k][cpy], X->hm[k][cpy], L->pstride, idx, hk);
+            stp<R>(M, ncell, 5 + k, idx, Ck);
+        }
+    }
 }
 
 // diagnostics of the moments buffer (used after set-up: residual 0)
@@ -1275,6 +1374,42 @@ __global__ __launch_bounds__(BLOCK) void k_diag_moments(const LatDev *L)
     block_reduce_store(part, L->partials + size_t(blockIdx.x) * NPART);
 }
 
+// Solute masses Sum eps C_k over fluid cells from the moments buffer: per
+// block partials (slots 0..nsp-1), then one block sums them in a fixed order
+// and leaves the totals in the first nsp partial slots.
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_solute_partials(const LatDev *L, int nsp)
+{
+    const uint32_t ncell = L->ncell;
+    const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (idx < ncell) {
+        const uint32_t nx = L->nx, nxy = nx * uint32_t(L->ny);
+        const int z = idx / nxy;
+        const uint32_t r = idx - uint32_t(z) * nxy;
+        const int y = r / nx, x = r - uint32_t(y) * nx;
+        int face;
+        if (cell_type(L, x, y, z, link_word(L, idx), face) == CELL_FLUID) {
+            const double e = L->uniform_eps ? L->eps_u : double(ldg<R>(L->eps, idx));
+            for (int k = 0; k < nsp; ++k) part[k] = e * double(ldp<R>(L->mom, ncell, 4 + k, idx));
+        }
+    }
+    block_reduce_store(part, L->partials + size_t(blockIdx.x) * NPART);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_solute_final(const LatDev *L, int nsp)
+{
+    double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int bk = threadIdx.x; bk < L->nblocks; bk += BLOCK) {
+        const double *p = L->partials + size_t(bk) * NPART;
+        for (int k = 0; k < nsp; ++k) v[k] += p[k];
+    }
+    __shared__ double out[NPART];
+    block_reduce_store(v, out);
+    __syncthreads();
+    if (threadIdx.x < nsp) L->partials[threadIdx.x] = out[threadIdx.x];
+}
+
 // decode the current populations of one lattice to the compute type
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, int src, typename Codec<S>::R *dst)
@@ -1283,8 +1418,9 @@ __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, in
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= ncell) return;
     using R = typename Codec<S>::R;
-    const void *P = which == 0 ? L->f[src] : L->h[src];
-    const void *M = which == 0 ? L->fm[src] : L->hm[src];
+    const MsDev *X = ms_of(L);
+    const void *P = which == 0 ? L->f[src] : (which == 1 ? L->h[src] : X->h[which - 2][src]);
+    const void *M = which == 0 ? L->fm[src] : (which == 1 ? L->hm[src] : X->hm[which - 2][src]);
     const R m = Codec<S>::split ? ldg<R>(M, idx) : R(0);
     for (int q = 0; q < NQ; ++q)
         dst[size_t(q) * ncell + idx] = fma(weight<R>(q), m, Codec<S>::load(at(plane<S>(P, L->pstride, q), idx)));

@@ -48,8 +48,12 @@ size_t plane_stride(const lbm_desc *d)
 
 struct Layout {
     size_t lat, err, diag, partials, eps, kinv, mom, rho1, links, f0, f1, h0, h1, fm0, fm1, hm0, hm1;
-    size_t fs, fs_cls, fs_w1, fs_w2, fs_mass, fs_lam, fs_rho, fs_share, fs_u, total;
+    size_t fs, fs_cls, fs_w1, fs_w2, fs_mass, fs_lam, fs_rho, fs_share, fs_u;
+    size_t ms, msx[MAXSPX][2], msm[MAXSPX][2], total;
 };
+
+// solutes beyond the first
+int extra_species(const lbm_desc *d) { return (d->physics == LBM_MISCIBLE && d->nspecies > 1) ? d->nspecies - 1 : 0; }
 
 bool split_storage(int storage) { return storage == LBM_BF16_SPLIT || storage == LBM_F16_SPLIT; }
 
@@ -108,6 +112,13 @@ bool valid_desc(const lbm_desc *d)
     if (d->solid_mask != 0 && d->solid_mask != 1) return false;
     if (d->full_tensor != 0 && d->full_tensor != 1) return false;
     if (d->solid_mask && d->physics == LBM_IMMISCIBLE && !is_fin(d->solid_contact_angle_deg)) return false;
+    if (d->nspecies < 0 || d->nspecies > LBM_MAX_SPECIES) return false;
+    if (d->nspecies > 1 && d->physics != LBM_MISCIBLE) return false;
+    for (int k = 0; k < extra_species(d); ++k) {
+        if (!(d->tau_d_x[k] > 0.5) || !is_fin(d->tau_d_x[k])) return false;
+        for (int f = 0; f < 6; ++f)
+            if (d->face[f].kind == LBM_FACE_RESERVOIR && !is_fin(d->face_conc_x[k][f])) return false;
+    }
     return true;
 }
 
@@ -124,7 +135,7 @@ Layout layout(const lbm_desc *d)
     L.partials = o;  o = align_up(o + nb * NPART * sizeof(double));
     L.eps = o;       o = align_up(o + n * rb);
     L.kinv = o;      o = align_up(o + (d->full_tensor ? 7 : 3) * n * rb);
-    L.mom = o;       o = align_up(o + 5 * n * rb);
+    L.mom = o;       o = align_up(o + (5 + extra_species(d)) * n * rb);
     L.rho1 = o;      if (d->physics == LBM_IMMISCIBLE) o = align_up(o + n * rb);
     L.links = o;     if (d->solid_mask) o = align_up(o + n * sizeof(uint32_t));
     const size_t ps = plane_stride(d);
@@ -150,6 +161,20 @@ Layout layout(const lbm_desc *d)
     L.fs_rho = o;    if (fs) o = align_up(o + n * sizeof(double));
     L.fs_share = o;  if (fs) o = align_up(o + n * sizeof(double));
     L.fs_u = o;      if (fs) o = align_up(o + 3 * n * sizeof(double));
+    // further solutes: the MsDev block, per solute two population copies and,
+    // split storage, two mass planes
+    const int nsx = extra_species(d);
+    L.ms = o;        if (nsx) o = align_up(o + sizeof(MsDev));
+    for (int k = 0; k < MAXSPX; ++k)
+        for (int c = 0; c < 2; ++c) {
+            L.msx[k][c] = o;
+            if (k < nsx) o = align_up(o + NQ * ps * sb);
+        }
+    for (int k = 0; k < MAXSPX; ++k)
+        for (int c = 0; c < 2; ++c) {
+            L.msm[k][c] = o;
+            if (k < nsx && sp) o = align_up(o + n * sizeof(float));
+        }
     L.total = o;
     return L;
 }
@@ -184,6 +209,7 @@ struct lbm_sim {
     Layout lay;
     LatDev host;        // host copy of the device parameter block
     FsDev fs;           // host copy of the free-surface block (free surface only)
+    MsDev ms;           // host copy of the further-solute block (several solutes only)
     LatDev *dev;        // the device parameter block (inside ws)
     long long steps;    // completed steps
     int cur;            // copy holding the current state
@@ -204,10 +230,10 @@ using Launch = void (*)(const BatchArgs &, int blocks, hipStream_t);
 // SIMD, which measured 2-3% slower on the FP32 miscible and two-fluid steps.
 constexpr size_t STEP_LDS_RESERVE = 33 * 1024;
 
-template <int P, class S, bool FT>
+template <int P, class S, bool FT, bool MS = false>
 void launch_step(const BatchArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<P, S, FT>), dim3(blocks), dim3(BLOCK), STEP_LDS_RESERVE, s, a);
+    hipLaunchKernelGGL((k_step<P, S, FT, MS>), dim3(blocks), dim3(BLOCK), STEP_LDS_RESERVE, s, a);
 }
 
 template <class S>
@@ -216,16 +242,16 @@ void launch_colour(const BatchArgs &a, int blocks, hipStream_t s)
     hipLaunchKernelGGL((k_colour<S>), dim3(blocks), dim3(BLOCK), 0, s, a);
 }
 
-template <int P, bool FT>
+template <int P, bool FT, bool MS = false>
 Launch step_for_storage(int storage)
 {
     switch (storage) {
-    case LBM_F64: return launch_step<P, double, FT>;
-    case LBM_F32: return launch_step<P, float, FT>;
-    case LBM_BF16_DEV: return launch_step<P, bf16_t, FT>;
-    case LBM_F16_DEV: return launch_step<P, f16_t, FT>;
-    case LBM_BF16_SPLIT: return launch_step<P, bf16s_t, FT>;
-    default: return launch_step<P, f16s_t, FT>;
+    case LBM_F64: return launch_step<P, double, FT, MS>;
+    case LBM_F32: return launch_step<P, float, FT, MS>;
+    case LBM_BF16_DEV: return launch_step<P, bf16_t, FT, MS>;
+    case LBM_F16_DEV: return launch_step<P, f16_t, FT, MS>;
+    case LBM_BF16_SPLIT: return launch_step<P, bf16s_t, FT, MS>;
+    default: return launch_step<P, f16s_t, FT, MS>;
     }
 }
 
@@ -233,6 +259,13 @@ template <int P>
 Launch step_for_tensor(int storage, bool full_tensor)
 {
     return full_tensor ? step_for_storage<P, true>(storage) : step_for_storage<P, false>(storage);
+}
+
+// miscible lattices with further solutes
+Launch step_for_species(int storage, bool full_tensor)
+{
+    return full_tensor ? step_for_storage<PH_MISCIBLE, true, true>(storage)
+                       : step_for_storage<PH_MISCIBLE, false, true>(storage);
 }
 
 // Free surface: the stream/collide pass on the step grid (a), the class
@@ -417,6 +450,8 @@ lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
         g.blocksm = tm;
         const bool ft = h0->host.full_tensor != 0;
         (ft ? fs_for_storage<true>(h0->d.storage) : fs_for_storage<false>(h0->d.storage))(g, h0->stream);
+    } else if (h0->host.ms) {
+        step_for_species(h0->d.storage, h0->host.full_tensor != 0)(a, total, h0->stream);
     } else {
         if (h0->d.physics == LBM_IMMISCIBLE) colour_launcher(h0->d.storage)(a, total, h0->stream);
         step_launcher(h0->d.physics, h0->d.storage, h0->host.full_tensor != 0)(a, total, h0->stream);
@@ -521,6 +556,20 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     D.mom = w + L.mom;
     D.rho1 = d->physics == LBM_IMMISCIBLE ? w + L.rho1 : nullptr;
     D.links = d->solid_mask ? w + L.links : nullptr;
+    if (extra_species(d)) {
+        MsDev &X = h->ms;
+        X.nsx = extra_species(d);
+        for (int k = 0; k < X.nsx; ++k) {
+            for (int c = 0; c < 2; ++c) {
+                X.h[k][c] = w + L.msx[k][c];
+                X.hm[k][c] = sp ? w + L.msm[k][c] : nullptr;
+            }
+            X.tau_d[k] = d->tau_d_x[k];
+            X.D[k] = (d->tau_d_x[k] - 0.5) / 3.0;
+            for (int f = 0; f < 6; ++f) X.face_conc[k][f] = d->face_conc_x[k][f];
+        }
+        D.ms = w + L.ms;
+    }
     if (d->physics == LBM_FREESURF) {
         FsDev &F = h->fs;
         F.cls = reinterpret_cast<unsigned char *>(w + L.fs_cls);
@@ -564,6 +613,9 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     if ((st = dev_err(hipMemcpyAsync(h->dev, &D, sizeof(LatDev), hipMemcpyHostToDevice, h->stream)))) return st;
     static const int zero = 0;
     if ((st = dev_err(hipMemcpyAsync(D.err, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream)))) return st;
+    if (D.ms &&
+        (st = dev_err(hipMemcpyAsync(const_cast<void *>(D.ms), &h->ms, sizeof(MsDev), hipMemcpyHostToDevice, h->stream))))
+        return st;
     if (D.fs) {
         static const double zero_mass = 0.0;
         if ((st = dev_err(hipMemcpyAsync(const_cast<void *>(D.fs), &h->fs, sizeof(FsDev), hipMemcpyHostToDevice,
@@ -644,15 +696,17 @@ lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n)
     lbm_sim *grp[MAXB];
     bool last[MAXB];
     for (int s = 0; s < maxs; ++s) {
-        // group the lattices still running by (physics, storage, permeability form)
+        // group the lattices still running by (physics, storage, permeability
+        // form, further solutes)
         for (int phys = LBM_SINGLE; phys <= LBM_FREESURF; ++phys)
-            for (int grp_key = 0; grp_key < 2 * (LBM_F16_SPLIT + 1); ++grp_key) {
-                const int stg = grp_key >> 1, ft = grp_key & 1;
+            for (int grp_key = 0; grp_key < 4 * (LBM_F16_SPLIT + 1); ++grp_key) {
+                const int stg = grp_key >> 2, ft = grp_key & 1, ms = (grp_key >> 1) & 1;
                 int k = 0;
                 for (int i = 0; i < n; ++i) {
                     lbm_sim *h = hs[i];
                     if (s >= nsteps[i] || h->d.physics != phys || h->d.storage != stg || h->host.full_tensor != ft)
                         continue;
+                    if ((h->host.ms != nullptr) != (ms != 0)) continue;
                     grp[k] = h;
                     last[k] = s + 1 == nsteps[i];
                     if (++k == MAXB) {
@@ -681,7 +735,9 @@ lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8
     lbm_status st;
     if (rho && (st = dev_err(hipMemcpyAsync(rho, M, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
     if (vel3 && (st = dev_err(hipMemcpyAsync(vel3, M + n * rb, 3 * n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
-    if (conc && (st = dev_err(hipMemcpyAsync(conc, M + 4 * n * rb, n * rb, hipMemcpyDeviceToDevice, h->stream)))) return st;
+    const size_t nconc = 1 + extra_species(&h->d);
+    if (conc && (st = dev_err(hipMemcpyAsync(conc, M + 4 * n * rb, nconc * n * rb, hipMemcpyDeviceToDevice, h->stream))))
+        return st;
     double dg[8];
     if ((st = dev_err(hipMemcpyAsync(dg, h->host.diag, sizeof(dg), hipMemcpyDeviceToHost, h->stream)))) return st;
     if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
@@ -691,7 +747,7 @@ lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8
 
 lbm_status lbm_populations(lbm_t h, int lattice, void *dst)
 {
-    if (!h || !dst || lattice < 0 || lattice > 1) return LBM_EINVAL;
+    if (!h || !dst || lattice < 0 || lattice > 1 + extra_species(&h->d)) return LBM_EINVAL;
     if (lattice == 1 && !two_lattices(h->d.physics)) return LBM_EINVAL;
     if (!h->ready) return LBM_ESTATE;
     if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
@@ -719,6 +775,27 @@ lbm_status lbm_populations(lbm_t h, int lattice, void *dst)
     lbm_status st;
     if ((st = dev_err(hipGetLastError()))) return st;
     return dev_err(hipStreamSynchronize(h->stream));
+}
+
+lbm_status lbm_solute_totals(lbm_t h, double *totals)
+{
+    if (!h || !totals || h->d.physics != LBM_MISCIBLE) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    const int nsp = 1 + extra_species(&h->d);
+    if (h->d.storage == LBM_F64)
+        hipLaunchKernelGGL(k_solute_partials<double>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev, nsp);
+    else
+        hipLaunchKernelGGL(k_solute_partials<float>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev, nsp);
+    hipLaunchKernelGGL(k_solute_final, dim3(1), dim3(BLOCK), 0, h->stream, (const LatDev *)h->dev, nsp);
+    lbm_status st;
+    if ((st = dev_err(hipGetLastError()))) return st;
+    double out[LBM_MAX_SPECIES];
+    if ((st = dev_err(hipMemcpyAsync(out, h->host.partials, nsp * sizeof(double), hipMemcpyDeviceToHost, h->stream))))
+        return st;
+    if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
+    memcpy(totals, out, nsp * sizeof(double));
+    return LBM_OK;
 }
 
 lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lost)

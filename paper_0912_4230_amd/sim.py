@@ -36,6 +36,12 @@ def make_desc(p: I.Problem, storage: int = B.LBM_F32, diag_every: int = 0) -> B.
     d.solid_mask = int(p.solid is not None)
     d.solid_contact_angle_deg = float(p.solid_angle)
     d.full_tensor = int(p.full_tensor)
+    d.nspecies = int(p.nspecies)
+    for k, t in enumerate(p.species_tau_d):
+        d.tau_d_x[k] = float(t)
+        for f in range(6):
+            cx = p.faces[f].conc_x
+            d.face_conc_x[k][f] = float(cx[k]) if len(cx) > k else 0.0
     return d
 
 
@@ -130,7 +136,8 @@ class Simulation:
         nx, ny, nz = self.shape
         rho = torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
         vel = torch.empty((3, nz, ny, nx), dtype=self.dtype, device=self.device)
-        conc = torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
+        ns = self.problem.nspecies if self.problem.physics == I.MISCIBLE else 1
+        conc = torch.empty(((ns,) if ns > 1 else ()) + (nz, ny, nx), dtype=self.dtype, device=self.device)
         diag = (C.c_double * 8)()
         B.lbm_moments(self.h, rho.data_ptr(), vel.data_ptr(), conc.data_ptr(), diag, check=check)
         return rho, vel, conc, np.array(diag[:])
@@ -147,6 +154,10 @@ class Simulation:
         out = torch.empty((19, nz, ny, nx), dtype=self.dtype, device=self.device)
         B.lbm_populations(self.h, lattice, out.data_ptr())
         return out
+
+    def solute_totals(self):
+        """Miscible: Sum eps C_k over fluid cells for every solute (FP64 list)."""
+        return B.lbm_solute_totals(self.h, self.problem.nspecies)
 
     def free_surface(self):
         """Free surface: (classes uint8 (nz,ny,nx) 0 gas / 1 interface / 2 liquid /
