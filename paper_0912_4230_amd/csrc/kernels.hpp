@@ -1015,12 +1015,30 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const BatchArgs a)
 {
     const int l = blockIdx.x;
     const LatDev *__restrict__ L = a.lat[l];
-    double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int bk = threadIdx.x; bk < L->nblocks; bk += BLOCK) {
-        const double *p = L->partials + size_t(bk) * NPART;
+    // four independent partial rows per iteration keep 36 loads in flight
+    constexpr int U = 4;
+    double w[U][NPART];
 #pragma unroll
-        for (int k = 0; k < NPART; ++k) v[k] = (k == 7) ? fmax(v[k], p[k]) : v[k] + p[k];
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) w[u][k] = 0.0;
+    const int nb = L->nblocks;
+    for (int bk0 = threadIdx.x; bk0 < nb; bk0 += U * BLOCK) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int bk = bk0 + u * BLOCK;
+            if (bk < nb) {
+                const double *p = L->partials + size_t(bk) * NPART;
+#pragma unroll
+                for (int k = 0; k < NPART; ++k) w[u][k] = (k == 7) ? fmax(w[u][k], p[k]) : w[u][k] + p[k];
+            }
+        }
     }
+    double v[NPART];
+#pragma unroll
+    for (int k = 0; k < NPART; ++k)
+        v[k] = (k == 7) ? fmax(fmax(w[0][k], w[1][k]), fmax(w[2][k], w[3][k]))
+                        : (w[0][k] + w[1][k]) + (w[2][k] + w[3][k]);
     __shared__ double out[NPART];
     block_reduce_store(v, out);
     __syncthreads();
