@@ -47,7 +47,8 @@
  *    the first solute's concentration;
  *  - free-surface mode (Sec. 3): liquid, interface and gas cells, mass
  *    exchange, reconstruction from gas cells and class conversion, with the
- *    readings stated beside fs_step below;
+ *    readings stated beside fs_step below; with surface tension (Sec. 5.4)
+ *    the gradient of Eq. macros is taken over the fill fraction lambda;
  *  - walls: halfway bounce-back; reservoirs: cells held at the equilibrium
  *    of (rho_bc, V' = 0, C_bc); the cells of an optional obstacle mask are
  *    solid like wall cells, with their own contact angle.
@@ -501,6 +502,22 @@ static void colour_gradient(const orc_state *s, int x, int y, int z, double F[3]
 
 static double solute_D(const orc_params *p) { return (p->tau_d - 0.5) / 3.0; }
 
+/* free surface with surface tension: the gradient of Eq. macros over the
+ * liquid, F = Sum_{i != 0} lambda(x + v_i) v_i with the fill fraction of the
+ * step's start (1 liquid, 0 gas, m / rho interface); a solid or out-of-box
+ * neighbour takes lambda(x) (no wall normal).                               */
+static void fs_gradient(const orc_state *s, int x, int y, int z, double F[3])
+{
+    long i0 = cidx(s, x, y, z);
+    double l0 = s->lam[i0];
+    F[0] = F[1] = F[2] = 0.0;
+    for (int q = 1; q < NQ; ++q) {
+        long j = neighbour(s, x, y, z, VEL[q][0], VEL[q][1], VEL[q][2]);
+        double l = (j < 0 || s->type[j] == CELL_SOLID) ? l0 : s->lam[j];
+        for (int a = 0; a < 3; ++a) F[a] += l * VEL[q][a];
+    }
+}
+
 /* pulled (streamed) population q of lattice L at fluid cell (x,y,z):
  * f_q(x) = f~_q(x - v_q), or f~_{opp q}(x) when x - v_q is solid
  * (halfway bounce-back).                                                   */
@@ -561,6 +578,7 @@ static void collide_cell(const orc_state *s, int x, int y, int z, double t,
 
     double F[3] = {0.0, 0.0, 0.0};
     if (p->physics == PHYS_IMMISCIBLE) colour_gradient(s, x, y, z, F);
+    else if (p->physics == PHYS_FREESURF && p->A != 0.0) fs_gradient(s, x, y, z, F);
 
     double eq[NQ], T[NQ];
     feq_dev(drho, Vp, eps, tau, p->A, F, eq);
