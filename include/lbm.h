@@ -96,7 +96,10 @@ typedef enum {
  * Then lambda = m / rho (1 for liquid, 0 for gas).  lbm_medium.c0 holds the
  * initial fill fraction: >= 1 liquid, <= 0 gas, else an interface cell with
  * m = c0 rho0; a liquid cell next to a gas cell starts as an interface cell
- * with m = rho0.  Reservoir faces are rejected.  lbm_moments reports lambda
+ * with m = rho0.  With A > 0 the surface-tension term of Eqs. equilc1/2 acts
+ * (Sec. 5.4) with the gradient of Eq. macros taken over the fill fraction,
+ * F = Sum_i lambda(x + v_i) v_i (a solid neighbour counts lambda(x)).
+ * Reservoir faces are rejected.  lbm_moments reports lambda
  * as the concentration; rho and V' of gas cells read 0; the diagnostics run
  * over liquid and interface cells, with diag[4] = the total liquid mass
  * (Sum of m over interface cells + Sum of rho over liquid cells).  The
@@ -151,7 +154,8 @@ typedef struct {
     double tau1, tau2;          /* two-fluid: relaxation times of fluid 1 and 2;
                                    nu = C nu_1 + (1 - C) nu_2 with C = rho_1 / rho */
     double tau_d;               /* miscible: solute relaxation time, D = (tau_d - 1/2)/3 */
-    double A;                   /* two-fluid: surface-tension strength (Eq. equilc1) */
+    double A;                   /* two-fluid or free surface: surface-tension strength
+                                   (Eq. equilc1); must be 0 in the other modes */
     double beta;                /* two-fluid: recolouring strength in [0, 1] */
     lbm_face face[6];           /* order: -x, +x, -y, +y, -z, +z */
     int diag_every;             /* FP64 diagnostics every k steps (0: only at the end

@@ -116,13 +116,23 @@ __device__ inline void coords(const LatDev *L, uint32_t idx, int &x, int &y, int
     x = r - uint32_t(y) * nx;
 }
 
+// fill fraction of the step's start of a cell of class c (1 liquid, 0 gas,
+// m / rho interface)
+__device__ inline double fs_lambda(const FsDev *F, int c, uint32_t j, int src)
+{
+    return c == FS_LIQ ? 1.0 : (c == FS_IF ? ldg<double>(F->lam[src], j) : 0.0);
+}
+
 // Pass 1.  Liquid and interface cells: pull; on links from gas cells the
 // rebuilt population f_q = f^eq_q + f^eq_opp(q) - f~_opp(q)(x) at the gas
 // density 1 and the velocity of the cell's own post-collision populations
 // (Eq. equilempty); mass exchange over the links to liquid and interface
 // neighbours (Eq. deltamass); the single-fluid collision with the porous
-// terms; interface cells store m and rho and flag FILL / EMPTY.
-template <class S, bool FT>
+// terms and, ST, the surface-tension term of Eqs. equilc1/2 with the gradient
+// of Eq. macros taken over the fill fraction, F = Sum lambda(x + v_q) v_q (a
+// solid neighbour takes lambda(x)); interface cells store m and rho and flag
+// FILL / EMPTY.
+template <class S, bool FT, bool ST = false>
 __global__ PLBM_STEP_ATTR void k_fs_step(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
@@ -204,9 +214,27 @@ __global__ PLBM_STEP_ATTR void k_fs_step(const BatchArgs a)
             }
             porous_force<R>(L, eps, kinv, nu, V, u, Fx);
         }
-        const R zero3[3] = {0, 0, 0};
-        const Coll<R> cl = make_coll<R>(drho, rho, omega, ie, u, Fx, R(0), zero3, R(0), R(0));
-        collide_f<R, false>(d, cl);
+        R Fs[3] = {0, 0, 0}, Fn = 0, iFn = 0, st = 0;
+        if constexpr (ST) {
+            if (L->A != 0.0) {
+                const double l0 = fs_lambda(F, cls, idx, src);
+                double g[3] = {0.0, 0.0, 0.0};
+                for_links([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    const uint32_t j = shifted<Q, 1>(b);
+                    const double l = shifted_solid<Q, 1>(b) ? l0 : fs_lambda(F, ldg<uint8_t>(F->cls, j), j, src);
+                    if constexpr (cx(Q) != 0) g[0] += cx(Q) > 0 ? l : -l;
+                    if constexpr (cy(Q) != 0) g[1] += cy(Q) > 0 ? l : -l;
+                    if constexpr (cz(Q) != 0) g[2] += cz(Q) > 0 ? l : -l;
+                });
+                for (int c = 0; c < 3; ++c) Fs[c] = R(g[c]);
+                Fn = sqrt(Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2]);
+                iFn = Fn > R(0) ? rcp(Fn) : R(0);
+                st = Fn > R(0) ? R(L->A) * eps * (R(0.5) + R(3) * nu) : R(0);
+            }
+        }
+        const Coll<R> cl = make_coll<R>(drho, rho, omega, ie, u, Fx, st, Fs, Fn, iFn);
+        collide_f<R, ST>(d, cl);
 
         if (cls == FS_IF) {
             const double r = double(rho);

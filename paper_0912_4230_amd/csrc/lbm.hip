@@ -105,7 +105,8 @@ bool valid_desc(const lbm_desc *d)
         if (!(d->a0 >= 0.0) || !(d->a1 >= 0.0) || !(d->a0 + d->a1 > 0.0)) return false;
         if (!is_fin(d->a0) || !is_fin(d->a1) || !is_fin(d->alpha) || !is_fin(d->k1) || !is_fin(d->k0)) return false;
         if (!(d->cap > 0.0)) return false;
-        if (d->A != 0.0) return false;  // surface tension belongs to the two-fluid model
+        // surface tension: the two-fluid model, or a free surface
+        if (d->physics == LBM_FREESURF ? !(d->A >= 0.0 && is_fin(d->A)) : d->A != 0.0) return false;
     }
     if (d->physics == LBM_MISCIBLE && (!(d->tau_d > 0.5) || !is_fin(d->tau_d))) return false;
     if (d->diag_every < 0) return false;
@@ -280,10 +281,10 @@ struct FsGrids {
 #define PLBM_FS_LDS 0
 #endif
 
-template <class S, bool FT>
+template <class S, bool FT, bool ST>
 void launch_fs(const FsGrids &g, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_fs_step<S, FT>), dim3(g.blocks), dim3(BLOCK), PLBM_FS_LDS, s, g.a);
+    hipLaunchKernelGGL((k_fs_step<S, FT, ST>), dim3(g.blocks), dim3(BLOCK), PLBM_FS_LDS, s, g.a);
     hipLaunchKernelGGL(k_fs_mark_fill, dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
     hipLaunchKernelGGL((k_fs_mark_empty<S>), dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
     hipLaunchKernelGGL(k_fs_excess, dim3(g.blocks16), dim3(BLOCK), 0, s, g.a16);
@@ -293,17 +294,25 @@ void launch_fs(const FsGrids &g, hipStream_t s)
 
 using FsLaunch = void (*)(const FsGrids &, hipStream_t);
 
-template <bool FT>
+template <bool FT, bool ST>
 FsLaunch fs_for_storage(int storage)
 {
     switch (storage) {
-    case LBM_F64: return launch_fs<double, FT>;
-    case LBM_F32: return launch_fs<float, FT>;
-    case LBM_BF16_DEV: return launch_fs<bf16_t, FT>;
-    case LBM_F16_DEV: return launch_fs<f16_t, FT>;
-    case LBM_BF16_SPLIT: return launch_fs<bf16s_t, FT>;
-    default: return launch_fs<f16s_t, FT>;
+    case LBM_F64: return launch_fs<double, FT, ST>;
+    case LBM_F32: return launch_fs<float, FT, ST>;
+    case LBM_BF16_DEV: return launch_fs<bf16_t, FT, ST>;
+    case LBM_F16_DEV: return launch_fs<f16_t, FT, ST>;
+    case LBM_BF16_SPLIT: return launch_fs<bf16s_t, FT, ST>;
+    default: return launch_fs<f16s_t, FT, ST>;
     }
+}
+
+// the surface-tension form when any lattice of the batch has A != 0 (with
+// A = 0 it computes exactly what the plain form does)
+FsLaunch fs_launcher(int storage, bool full_tensor, bool st)
+{
+    if (st) return full_tensor ? fs_for_storage<true, true>(storage) : fs_for_storage<false, true>(storage);
+    return full_tensor ? fs_for_storage<true, false>(storage) : fs_for_storage<false, false>(storage);
 }
 
 Launch step_launcher(int physics, int storage, bool full_tensor)
@@ -448,8 +457,9 @@ lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
         g.am.total_blocks = tm;
         g.blocks16 = t16;
         g.blocksm = tm;
-        const bool ft = h0->host.full_tensor != 0;
-        (ft ? fs_for_storage<true>(h0->d.storage) : fs_for_storage<false>(h0->d.storage))(g, h0->stream);
+        bool st = false;
+        for (int i = 0; i < n; ++i) st = st || hs[i]->d.A != 0.0;
+        fs_launcher(h0->d.storage, h0->host.full_tensor != 0, st)(g, h0->stream);
     } else if (h0->host.ms) {
         step_for_species(h0->d.storage, h0->host.full_tensor != 0)(a, total, h0->stream);
     } else {

@@ -461,6 +461,21 @@ def slab(shape=(48, 4, 3), lo=8, hi=20, speed=0.05, tau=0.8) -> Problem:
     return p.fill_defaults()
 
 
+def square(shape=(100, 100, 1), side=20, tau=0.7, A=0.001, beta=0.7) -> Problem:
+    """The surface-smoothing set-up of Sec. 5.4 in the two-fluid model: a square
+    (a cube when nz > 1) of fluid 1 with the given side at the box centre, both
+    fluids at tau = 0.7 (the droplet's), surface-tension strength A, periodic
+    box, no force and no porous medium."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    inside = (np.abs(x - (nx - 1) / 2.0) < side / 2.0) & (np.abs(y - (ny - 1) / 2.0) < side / 2.0)
+    if nz > 1:
+        inside &= np.abs(z - (nz - 1) / 2.0) < side / 2.0
+    p = Problem(shape=tuple(shape), physics=IMMISCIBLE, tau1=tau, tau2=tau, A=A, beta=beta,
+                c0=inside.astype(np.float64))
+    return p.fill_defaults()
+
+
 def sphere_obstacles(shape, seed: int = 0, solid_fraction: float = 0.1, radius=(2.0, 4.0),
                      keep_planes=(0,)) -> np.ndarray:
     """Seeded obstacle mask: spheres with radii uniform in `radius` and centres

@@ -98,6 +98,23 @@ def test_ragged_box_f64():
     _compare(p, [30, 90, 200], diag_every=13, name="ragged drop 13x11x17")
 
 
+def test_surface_tension_drop_f64():
+    """Surface tension at the free surface (Sec. 5.4): a 2D drop relaxing from
+    a square and a 3D drop falling into a porous medium with A != 0."""
+    n = 40
+    p = I.falling_drop(shape=(n, n, 1), radius=0.0, G=0.0, tau=0.7, wall=False)
+    z, y, x = np.meshgrid(np.arange(1), np.arange(n), np.arange(n), indexing="ij")
+    p.c0 = ((np.abs(x - 19.5) < 7) & (np.abs(y - 19.5) < 7)).astype(float)
+    p.A = 0.003
+    _compare(p, [1, 100, 400, 900], diag_every=50, name="square with surface tension 40x40")
+    shape = (14, 12, 18)
+    q = I.falling_drop(shape=shape, radius=4.2, centre=(7.0, 6.0, 11.5), G=3e-4, tau=0.8, axis=2)
+    eps, kinv = I.spruce_medium(shape, seed=5, ratio=20.0)
+    q.eps, q.kinv = eps, kinv * 1e-2
+    q.A = 0.002
+    _compare(q, [60, 200], name="3D drop with surface tension 14x12x18")
+
+
 def test_full_tensor_medium_f64():
     shape = (16, 13, 15)
     p = I.falling_drop(shape=shape, radius=4.0, centre=(8.0, 6.5, 9.0), G=4e-4, tau=0.9, axis=2)
@@ -239,3 +256,49 @@ def test_paper_droplet_mass_and_impact():
     assert worst < 1e-10
     assert t_hit is not None and abs(t_hit / 10600.0 - 1.0) < 0.05
     sim.close()
+
+
+def test_paper_surface_smoothing():
+    """Sec. 5.4 as the paper ran it: a 20 x 20 square of liquid in a 100 x 100 x 1
+    box with the free surface, rho = 1, tau = 0.7, A = 0.001, no force, 10000
+    steps: the square becomes round (radius RMS / mean 0.104 -> below 0.015)
+    and keeps its mass; without the term it stays a square."""
+    from paper_0912_4230_amd.sim import Simulation
+    n = 100
+    p = I.falling_drop(shape=(n, n, 1), radius=0.0, G=0.0, tau=0.7, wall=False)
+    z, y, x = np.meshgrid(np.arange(1), np.arange(n), np.arange(n), indexing="ij")
+    p.c0 = ((np.abs(x - 49.5) < 10) & (np.abs(y - 49.5) < 10)).astype(float)
+    out = {}
+    for A in (0.001, 0.0):
+        p.A = A
+        sim = Simulation(p, storage="f32")
+        M0 = sim.diag()[4]
+        lam0 = sim.moments()[2].double().cpu().numpy()
+        sim.step(10000)
+        rho, vel, lam, dg = sim.moments()
+        out[A] = (_roundness(lam0), _roundness(lam.double().cpu().numpy()), dg[4] / M0 - 1.0)
+        sim.close()
+    print(f"[physics] paper surface smoothing 100x100x1 x10000: A=0.001 roundness {out[0.001][0]:.3f} -> "
+          f"{out[0.001][1]:.4f} (mass drift {out[0.001][2]:.1e}); A=0 {out[0.0][0]:.3f} -> {out[0.0][1]:.3f}",
+          flush=True)
+    assert out[0.001][0] > 0.09 and out[0.001][1] < 0.015
+    assert abs(out[0.0][1] - out[0.0][0]) < 1e-3
+    assert abs(out[0.001][2]) < 1e-5
+
+
+def _roundness(lam):
+    c = lam[0]
+    n = c.shape[0]
+    cx = (c * np.arange(c.shape[1])[None, :]).sum() / c.sum()
+    cy = (c * np.arange(n)[:, None]).sum() / c.sum()
+    pts = []
+    for ang in np.linspace(0, 2 * np.pi, 180, endpoint=False):
+        r = np.arange(0, n / 2 - 2, 0.05)
+        px, py = cx + r * np.cos(ang), cy + r * np.sin(ang)
+        ix, iy = np.floor(px).astype(int), np.floor(py).astype(int)
+        fx, fy = px - ix, py - iy
+        v = ((1 - fx) * (1 - fy) * c[iy, ix] + fx * (1 - fy) * c[iy, ix + 1]
+             + (1 - fx) * fy * c[iy + 1, ix] + fx * fy * c[iy + 1, ix + 1])
+        pts.append(r[np.nonzero(v < 0.5)[0][0]])
+    pts = np.array(pts)
+    return pts.std() / pts.mean()
