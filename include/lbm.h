@@ -240,10 +240,12 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m);
 /* Advance nsteps >= 0 time steps, asynchronously on the handle's stream. */
 lbm_status lbm_step(lbm_t h, int nsteps);
 
-/* Advance n lattices by nsteps[i] steps each, with one kernel launch per
- * step for all lattices of the same physics and storage (continuous
- * batching).  All handles must share one stream.  Per-lattice results are
- * bitwise identical to lbm_step on the same handle. */
+/* Advance n lattices by nsteps[i] steps each, with one launch sequence per
+ * step for all lattices of the same physics, storage, permeability form
+ * (diagonal or full tensor) and solute count form (one, or more) (continuous
+ * batching; up to 64 lattices per launch).  All handles must share one
+ * stream.  Per-lattice results are bitwise identical to lbm_step on the same
+ * handle. */
 lbm_status lbm_step_batch(lbm_t *hs, const int *nsteps, int n);
 
 /* Copy the moments of the last step (density rho, corrected velocity V' as

@@ -163,3 +163,41 @@ def test_free_surface_descriptions():
     # every free-surface generator gives a valid description
     for g in (I.falling_drop(), I.falling_drop(shape=(12, 10, 9), radius=3.0, axis=2), I.pool(), I.slab()):
         assert B.lbm_workspace_bytes(make_desc(g, B.LBM_F64)) > 0
+
+
+def test_species_and_surface_tension_descriptions():
+    """Several solutes: 1-4 and miscible only, further relaxation times > 1/2;
+    surface tension: two-fluid or free surface, A >= 0.  Rejected before any
+    GPU call (lbm_workspace_bytes = 0)."""
+    import numpy as np
+    from paper_0912_4230_amd import inputs as I
+    from paper_0912_4230_amd.sim import make_desc
+    p = I.miscible(shape=(16, 12, 10), seed=0)
+    base = B.lbm_workspace_bytes(make_desc(p, B.LBM_F32))
+    p.species_tau_d = (0.8, 1.2)
+    d = make_desc(p, B.LBM_F32)
+    ws3 = B.lbm_workspace_bytes(d)
+    # two more lattices, two copies each, plus two moment planes
+    assert ws3 > base + 2 * 2 * 19 * 16 * 12 * 10 * 4
+    d.nspecies = 5
+    assert B.lbm_workspace_bytes(d) == 0
+    d.nspecies = 3
+    d.tau_d_x[1] = 0.5
+    assert B.lbm_workspace_bytes(d) == 0
+    d.tau_d_x[1] = float("nan")
+    assert B.lbm_workspace_bytes(d) == 0
+    q = I.Problem(shape=(8, 8, 8)).fill_defaults()
+    dq = make_desc(q, B.LBM_F32)
+    dq.nspecies = 2
+    assert B.lbm_workspace_bytes(dq) == 0
+    dq.nspecies = 1
+    assert B.lbm_workspace_bytes(dq) > 0
+    # surface tension: free surface yes (A >= 0), single fluid no
+    fs = I.slab()
+    dfs = make_desc(fs, B.LBM_F32)
+    dfs.A = 0.001
+    assert B.lbm_workspace_bytes(dfs) > 0
+    dfs.A = -0.001
+    assert B.lbm_workspace_bytes(dfs) == 0
+    dq.A = 0.001
+    assert B.lbm_workspace_bytes(dq) == 0
