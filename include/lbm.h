@@ -263,7 +263,8 @@ lbm_status lbm_moments(lbm_t h, void *rho, void *vel3, void *conc, double diag[8
 /* Current post-collision populations of lattice 0 (hydrodynamic, as
  * deviations f_i - w_i) or 1 (second lattice, as is; with several solutes
  * 1..nspecies are the solutes), decoded to the real type: 19 planes in the
- * direction order of lbm_lattice(). */
+ * direction order of lbm_lattice().  Free surface: the values of gas cells
+ * are left over from earlier steps and carry no meaning. */
 lbm_status lbm_populations(lbm_t h, int lattice, void *dst);
 
 /* Miscible mode: the mass of every solute over the fluid cells of the last
