@@ -38,14 +38,7 @@ enum { CELL_FLUID = 0, CELL_SOLID = 1, CELL_RES = 2 };
 #ifndef PLBM_SLAB
 #define PLBM_SLAB 0
 #endif
-#ifndef PLBM_WPE
-#define PLBM_WPE 0
-#endif
-#if PLBM_WPE > 0
-#define PLBM_STEP_ATTR __launch_bounds__(PLBM_BLOCK) __attribute__((amdgpu_waves_per_eu(PLBM_WPE)))
-#else
 #define PLBM_STEP_ATTR __launch_bounds__(PLBM_BLOCK)
-#endif
 
 constexpr int BLOCK = PLBM_BLOCK;
 constexpr int MAXB = 64;     // lattices per batched launch
@@ -753,8 +746,20 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 // of the launch has a full permeability tensor (eigenframe form).  MS
 // (miscible): the lattices may carry further solutes, updated after the
 // first with the same V' (a runtime count per lattice, possibly 0).
+// Waves per SIMD the step is compiled for.  The miscible step with BF16
+// deviations or split 16-bit storage (diagonal K, one solute) fits in 96
+// VGPRs at 5 waves without spills and runs 4-6% faster there; every other
+// form keeps the compiler's own choice (1 = no constraint; the FP32 and FP64
+// code is the same as without the attribute) and the LDS reserve that holds
+// it at 4 waves.
+template <int PHYS, class S, bool FT, bool MS> struct StepWaves { static constexpr int value = 1; };
+template <> struct StepWaves<PH_MISCIBLE, bf16_t, false, false> { static constexpr int value = 5; };
+template <> struct StepWaves<PH_MISCIBLE, bf16s_t, false, false> { static constexpr int value = 5; };
+template <> struct StepWaves<PH_MISCIBLE, f16s_t, false, false> { static constexpr int value = 5; };
+
 template <int PHYS, class S, bool FT = false, bool MS = false>
-__global__ PLBM_STEP_ATTR void k_step(const BatchArgs a)
+__global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, FT, MS>::value))) void k_step(
+    const BatchArgs a)
 {
     using R = typename Codec<S>::R;
     const int gb = xcd_remap(blockIdx.x, a.total_blocks);

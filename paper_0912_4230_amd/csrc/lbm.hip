@@ -234,7 +234,8 @@ constexpr size_t STEP_LDS_RESERVE = 33 * 1024;
 template <int P, class S, bool FT, bool MS = false>
 void launch_step(const BatchArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<P, S, FT, MS>), dim3(blocks), dim3(BLOCK), STEP_LDS_RESERVE, s, a);
+    const size_t lds = StepWaves<P, S, FT, MS>::value == 5 ? 0 : STEP_LDS_RESERVE;
+    hipLaunchKernelGGL((k_step<P, S, FT, MS>), dim3(blocks), dim3(BLOCK), lds, s, a);
 }
 
 template <class S>
