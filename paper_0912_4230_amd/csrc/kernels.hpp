@@ -945,7 +945,15 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
         for (int k = 0; k < nsx; ++k) {
             R hk[NQ];
             if (type == CELL_FLUID) {
-                pull_all<S>(X->h[k][src], X->hm[k][src], L->pstride, idx, bx, hk);
+                // an opaque copy of the neighbour offsets: without it the
+                // compiler hoists the 18 (split codecs: 36) per-link byte
+                // offsets out of the loop and keeps them live across it (split
+                // forms 211-218 VGPRs, 2 waves per SIMD); computed inside,
+                // every form fits in 116-120 and runs 4 waves
+                Nbr bk = bx;
+                asm volatile("" : "+v"(bk.xm), "+v"(bk.x0), "+v"(bk.xp), "+v"(bk.ym), "+v"(bk.y0), "+v"(bk.yp),
+                             "+v"(bk.zm), "+v"(bk.z0), "+v"(bk.zp), "+v"(bk.bb));
+                pull_all<S>(X->h[k][src], X->hm[k][src], L->pstride, idx, bk, hk);
                 R sh = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) sh += hk[q];
