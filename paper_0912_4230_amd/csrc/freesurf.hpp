@@ -59,6 +59,34 @@ __device__ inline void for_links(Fn &&fn)
     if constexpr (Q + 1 < NQ) for_links<Q + 1>(fn);
 }
 
+// f(std::integral_constant<int, Q>) for Q = A .. B - 1
+template <int A, int B, class Fn>
+__device__ inline void for_range(Fn &&fn)
+{
+    if constexpr (A < B) {
+        fn(std::integral_constant<int, A>{});
+        for_range<A + 1, B>(fn);
+    }
+}
+
+// Per-link neighbour data (classes, fill fractions) is read in groups of
+// FS_GROUP links: all loads of a group are issued before any is used, so an
+// interface cell waits for six round trips instead of one or two per link
+// (measured on the 256^3 penetration step: 7-9% faster than per link; groups
+// of 1, 2 and 6 are slower than 3, the larger ones from register pressure).
+// Every neighbour index is wrapped into the lattice, so the loads need no
+// guard; the values of solid links are replaced after the load.
+constexpr int FS_GROUP = 3;
+static_assert((NQ - 1) % FS_GROUP == 0, "whole groups cover the 18 links");
+
+// fn(std::integral_constant<int, Q0>) for the first link Q0 of every group
+template <int Q0 = 1, class Fn>
+__device__ inline void for_groups(Fn &&fn)
+{
+    fn(std::integral_constant<int, Q0>{});
+    if constexpr (Q0 + FS_GROUP < NQ) for_groups<Q0 + FS_GROUP>(fn);
+}
+
 // the 19 populations of cell idx of one copy, decoded
 template <class S>
 __device__ inline void load_cell(const void *P, const void *M, uint32_t n, uint32_t idx, typename Codec<S>::R *o)
@@ -134,11 +162,10 @@ __device__ inline double fs_lambda(const FsDev *F, int c, uint32_t j, int src)
 // FILL / EMPTY.
 // Waves per SIMD the stream/collide pass is compiled for.  The 16-bit forms
 // without tensor or surface tension take 5 (FP16 deviations) or 6 waves and
-// spill 12-44 bytes per lane (BF16: one 8-byte store per live cell, the
-// reloads in the interface branch, which holds three sets of 19 populations);
-// measured on the 256^3 penetration step they are 4-6% faster than at their
-// natural 4-5 waves.  FP32 at 6 waves is 2-4% slower;
-// every other form keeps the compiler's choice.
+// spill 40-52 bytes per lane (in the BF16 form all spill code sits in the
+// interface branch, which holds three sets of 19 populations); on the 256^3
+// penetration step they are 13% faster than at their natural 4-5 waves.  FP32
+// at 6 waves is 2-4% slower; every other form keeps the compiler's choice.
 template <class S, bool FT, bool ST> struct FsWaves { static constexpr int value = 1; };
 template <> struct FsWaves<bf16_t, false, false> { static constexpr int value = 6; };
 template <> struct FsWaves<bf16s_t, false, false> { static constexpr int value = 6; };
@@ -184,18 +211,28 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
             equilibrium<R>(R(1), ou, ie, eA);
             const double lx = ldg<double>(F->lam[src], idx);
             double dm = 0.0;
-            for_links([&](auto qc) {
-                constexpr int Q = decltype(qc)::value;
-                // the neighbour x - v_Q, whose population Q streams in and to
+            for_groups([&](auto gc) {
+                constexpr int Q0 = decltype(gc)::value;
+                int cn[FS_GROUP];
+                double ln[FS_GROUP];
+                // the neighbours x - v_Q, whose population Q streams in and to
                 // which the population opp(Q) of this cell streams out
-                const uint32_t j = shifted<Q, -1>(b);
-                const int cj = shifted_solid<Q, -1>(b) ? FS_SOLID : int(ldg<uint8_t>(F->cls, j));
-                if (cj == FS_GAS) {
-                    d[Q] = eA[Q] + eA[opp(Q)] - o[opp(Q)];
-                } else if (cj != FS_SOLID) {
-                    const double fl = double(d[Q]) - double(o[opp(Q)]);
-                    dm += cj == FS_LIQ ? fl : fl * (0.5 * (lx + ldg<double>(F->lam[src], j)));
-                }
+                for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    const uint32_t j = shifted<Q, -1>(b);
+                    cn[Q - Q0] = ldg<uint8_t>(F->cls, j);
+                    ln[Q - Q0] = ldg<double>(F->lam[src], j);
+                });
+                for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    const int cj = shifted_solid<Q, -1>(b) ? FS_SOLID : cn[Q - Q0];
+                    if (cj == FS_GAS) {
+                        d[Q] = eA[Q] + eA[opp(Q)] - o[opp(Q)];
+                    } else if (cj != FS_SOLID) {
+                        const double fl = double(d[Q]) - double(o[opp(Q)]);
+                        dm += cj == FS_LIQ ? fl : fl * (0.5 * (lx + ln[Q - Q0]));
+                    }
+                });
             });
             m = ldg<double>(F->mass, idx) + dm;
         }
@@ -232,13 +269,29 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
             if (L->A != 0.0) {
                 const double l0 = fs_lambda(F, cls, idx, src);
                 double g[3] = {0.0, 0.0, 0.0};
-                for_links([&](auto qc) {
-                    constexpr int Q = decltype(qc)::value;
-                    const uint32_t j = shifted<Q, 1>(b);
-                    const double l = shifted_solid<Q, 1>(b) ? l0 : fs_lambda(F, ldg<uint8_t>(F->cls, j), j, src);
-                    if constexpr (cx(Q) != 0) g[0] += cx(Q) > 0 ? l : -l;
-                    if constexpr (cy(Q) != 0) g[1] += cy(Q) > 0 ? l : -l;
-                    if constexpr (cz(Q) != 0) g[2] += cz(Q) > 0 ? l : -l;
+                for_groups([&](auto gc) {
+                    constexpr int Q0 = decltype(gc)::value;
+                    int cn[FS_GROUP];
+                    double ln[FS_GROUP];
+                    for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;
+                        cn[Q - Q0] = ldg<uint8_t>(F->cls, shifted<Q, 1>(b));
+                    });
+                    // the fill fraction is read only where the neighbour is an
+                    // interface cell (interior liquid cells read none)
+                    for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;
+                        const int c = cn[Q - Q0];
+                        ln[Q - Q0] = shifted_solid<Q, 1>(b) ? l0
+                                   : (c == FS_LIQ ? 1.0 : (c == FS_IF ? ldg<double>(F->lam[src], shifted<Q, 1>(b)) : 0.0));
+                    });
+                    for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;
+                        const double l = ln[Q - Q0];
+                        if constexpr (cx(Q) != 0) g[0] += cx(Q) > 0 ? l : -l;
+                        if constexpr (cy(Q) != 0) g[1] += cy(Q) > 0 ? l : -l;
+                        if constexpr (cz(Q) != 0) g[2] += cz(Q) > 0 ? l : -l;
+                    });
                 });
                 for (int c = 0; c < 3; ++c) Fs[c] = R(g[c]);
                 Fn = sqrt(Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2]);
