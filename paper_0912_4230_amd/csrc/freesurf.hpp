@@ -47,7 +47,26 @@ struct FsDev {
     double *u;              // step, every liquid or interface cell on moment steps
     double *share;          // excess mass per receiver of each converting cell
     double *lost;           // accumulated excess mass that found no receiver
+    // launch order of pass 1, one set per population copy (as lam): rows of
+    // 256 cells that hold interface cells, in the order they were listed, the
+    // number listed, and per row 1 + its position in the list (0: not listed)
+    uint32_t *hlist[2];
+    uint32_t *hcount[2];
+    uint32_t *hpos[2];
 };
+
+// List a row for the next pass 1 (buffer buf), once: the first caller claims
+// it, takes a position and records it; later callers find it claimed.
+// Positions stay below the row count nrow (a row is listed at most once
+// until it is unlisted); the bound on the store guards the list regardless.
+__device__ inline void fs_list_row(const FsDev *F, int buf, uint32_t row, uint32_t nrow)
+{
+    if (atomicCAS(F->hpos[buf] + row, 0u, ~0u) == 0u) {
+        const uint32_t pos = atomicAdd(F->hcount[buf], 1u);
+        if (pos < nrow) F->hlist[buf][pos] = row;
+        atomicExch(F->hpos[buf] + row, pos + 1u);
+    }
+}
 
 __device__ inline const FsDev *fs_of(const LatDev *L) { return static_cast<const FsDev *>(L->fs); }
 
@@ -172,25 +191,51 @@ template <> struct FsWaves<bf16s_t, false, false> { static constexpr int value =
 template <> struct FsWaves<f16s_t, false, false> { static constexpr int value = 6; };
 template <> struct FsWaves<f16_t, false, false> { static constexpr int value = 5; };
 
+//
+// Launch order: a lattice's blocks are a prefix of `cap` blocks followed by one
+// block per row of 256 cells.  Prefix block i processes the i-th listed row (a
+// row that held interface cells at the previous step or gained them in its
+// class passes) and exits if fewer are listed; a row block exits if its row
+// was listed within the first `cap`.  Interface cells wait on their
+// neighbours' classes and fill fractions, so their waves run longest; started
+// first, they overlap with the bulk instead of trailing it.  Every row is
+// processed exactly once, and no cell reads what another writes in this pass,
+// so the order changes no result.
+
 template <class S, bool FT, bool ST = false>
 __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>::value))) void k_fs_step(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
-    const FsCell c = fs_cell(a);
+    FsCell c = fs_cell(a);
     const LatDev *__restrict__ L = c.L;
     const FsDev *__restrict__ F = c.F;
-    const uint32_t idx = c.idx, ncell = c.ncell;
     const int src = c.flags & 1, dst = src ^ 1;
+    const uint32_t nrow = (c.ncell + BLOCK - 1) / BLOCK;
+    const uint32_t cap = uint32_t(a.blk_start[c.l + 1] - a.blk_start[c.l]) - nrow;
+    const bool prefix = uint32_t(c.lb) < cap;
+    uint32_t row;
+    if (prefix) {
+        if (uint32_t(c.lb) >= ldg<uint32_t>(F->hcount[src], 0)) return;   // uniform over the block
+        row = ldg<uint32_t>(F->hlist[src], uint32_t(c.lb));
+        if (row >= nrow) return;
+    } else {
+        row = uint32_t(c.lb) - cap;
+    }
+    c.idx = row * BLOCK + threadIdx.x;
+    const uint32_t idx = c.idx, ncell = c.ncell;
     const bool mom = (c.flags & 2) != 0;
     const R nuc = R(a.nuc[c.l]);
 
     int cls = FS_SOLID, x = 0, y = 0, z = 0;
     uint32_t lw = 0;
+    // a row block reads whether the prefix took its row with its class
+    const uint32_t listed = prefix ? 0u : ldg<uint32_t>(F->hpos[src], row);
     if (idx < ncell) {
         coords(L, idx, x, y, z);
         lw = link_word(L, idx);
         cls = ldg<uint8_t>(F->cls, idx);
     }
+    if (listed != 0u && listed <= cap) return;   // uniform over the block
     const bool live = cls == FS_IF || cls == FS_LIQ;
     R d[NQ];
     unsigned char flag = 0;
@@ -322,6 +367,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
     // waves made only of gas and solid cells store nothing
     if (idx < ncell && __builtin_amdgcn_ballot_w64(live) != 0)
         store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
+    if (__builtin_amdgcn_ballot_w64(cls == FS_IF) != 0 && (threadIdx.x & 63) == 0) fs_list_row(F, dst, row, nrow);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,6 +437,16 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
     const FsTile t = fs_tile(a);
     if (t.base >= t.ncell) return;
     const FsDev *__restrict__ F = t.F;
+    {
+        // the launch-order list pass 1 has just used serves the next step
+        // again: unlist its rows (the count is cleared by the next pass)
+        const int src = t.flags & 1;
+        const uint32_t tn = t.base / FS_CPT, nrow = (t.ncell + BLOCK - 1) / BLOCK;
+        if (tn < nrow && tn < ldg<uint32_t>(F->hcount[src], 0)) {
+            const uint32_t r = ldg<uint32_t>(F->hlist[src], tn);
+            if (r < nrow) stg<uint32_t>(F->hpos[src], r, 0u);
+        }
+    }
     const u32x4 f = ld16(F->w1, t.base);
     if (!any_byte(f)) return;
     for (int k = 0; k < FS_CPT; ++k) {
@@ -421,6 +477,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
     const FsDev *__restrict__ F = t.F;
     const int dst = (t.flags & 1) ^ 1;
     const bool mom = (t.flags & 2) != 0;
+    if (t.base == 0) stg<uint32_t>(F->hcount[dst ^ 1], 0, 0u);   // the list unlisted by the last pass
     const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
     if (!any_byte(f) && !any_byte(m2)) return;
     for (int k = 0; k < FS_CPT; ++k) {
@@ -575,6 +632,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
         if (w2 & (FS_BORN | FS_TO_IF)) {
             stg<uint8_t>(F->cls, idx, FS_IF);
             stg<uint8_t>(F->w2, idx, 0);
+            fs_list_row(F, dst, idx / BLOCK, (t.ncell + BLOCK - 1) / BLOCK);
         }
     }
 }
@@ -643,9 +701,9 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const 
 {
     const uint32_t ncell = L->ncell;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
+    const FsDev *F = fs_of(L);
     double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (idx < ncell) {
-        const FsDev *F = fs_of(L);
         int cls = ldg<uint8_t>(F->w1, idx);
         if (cls == FS_LIQ) {
             int x, y, z;
@@ -678,6 +736,15 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const 
             const R u[3] = {ldp<R>(M, ncell, 1, idx), ldp<R>(M, ncell, 2, idx), ldp<R>(M, ncell, 3, idx)};
             diag_contrib<R>(part, ldg<R>(M, idx), u, R(l), R(0), u);
             part[4] = l * r0;
+        }
+    }
+    // empty launch-order lists
+    if (threadIdx.x == 0) {
+        stg<uint32_t>(F->hpos[0], blockIdx.x, 0u);
+        stg<uint32_t>(F->hpos[1], blockIdx.x, 0u);
+        if (blockIdx.x == 0) {
+            stg<uint32_t>(F->hcount[0], 0, 0u);
+            stg<uint32_t>(F->hcount[1], 0, 0u);
         }
     }
     block_reduce_store(part, L->partials + size_t(blockIdx.x) * NPART);

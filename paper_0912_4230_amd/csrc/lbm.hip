@@ -8,6 +8,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "kernels.hpp"
@@ -48,7 +49,7 @@ size_t plane_stride(const lbm_desc *d)
 
 struct Layout {
     size_t lat, err, diag, partials, eps, kinv, mom, rho1, links, f0, f1, h0, h1, fm0, fm1, hm0, hm1;
-    size_t fs, fs_cls, fs_w1, fs_w2, fs_mass, fs_lam, fs_rho, fs_share, fs_u;
+    size_t fs, fs_cls, fs_w1, fs_w2, fs_mass, fs_lam, fs_rho, fs_share, fs_u, fs_hot;
     size_t ms, msx[MAXSPX][2], msm[MAXSPX][2], total;
 };
 
@@ -152,7 +153,8 @@ Layout layout(const lbm_desc *d)
     const bool fs = d->physics == LBM_FREESURF;
     // free surface: the FsDev block (+ the lost-mass counter), three byte
     // planes, five double planes (m, two of lambda, rho, share) and the 3
-    // double planes of V'
+    // double planes of V', and two launch-order sets (row list, per-row
+    // positions, count)
     L.fs = o;        if (fs) o = align_up(o + sizeof(FsDev) + sizeof(double));
     L.fs_cls = o;    if (fs) o = align_up(o + n);
     L.fs_w1 = o;     if (fs) o = align_up(o + n);
@@ -162,6 +164,8 @@ Layout layout(const lbm_desc *d)
     L.fs_rho = o;    if (fs) o = align_up(o + n * sizeof(double));
     L.fs_share = o;  if (fs) o = align_up(o + n * sizeof(double));
     L.fs_u = o;      if (fs) o = align_up(o + 3 * n * sizeof(double));
+    const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4);
+    L.fs_hot = o;    if (fs) o = align_up(o + 2 * (2 * rows4 + 256));
     // further solutes: the MsDev block, per solute two population copies and,
     // split storage, two mass planes
     const int nsx = extra_species(d);
@@ -273,6 +277,10 @@ Launch step_for_species(int storage, bool full_tensor)
 // Free surface: the stream/collide pass on the step grid (a), the class
 // passes on the grid of BLOCK * FS_CPT cells per block (a16), the moments
 // pass on the step grid of the lattices at a moment step (am, may be empty).
+// Blocks of the free-surface pass 1 that take the listed rows first: 1/32 of
+// the rows, at least 64 (all rows of a smaller lattice).
+int fs_prefix_blocks(int rows) { return std::min(rows, std::max(64, rows / 32)); }
+
 struct FsGrids {
     BatchArgs a, a16, am;
     int blocks, blocks16, blocksm;
@@ -429,9 +437,18 @@ lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
     a.total_blocks = total;
     const lbm_sim *h0 = hs[0];
     if (h0->d.physics == LBM_FREESURF) {
+        // pass 1: per lattice a prefix of blocks for the rows listed as
+        // holding interface cells, then one block per row
         FsGrids g;
         g.a = a;
-        g.blocks = total;
+        int tp = 0;
+        for (int i = 0; i < n; ++i) {
+            g.a.blk_start[i] = tp;
+            tp += fs_prefix_blocks(hs[i]->nblocks) + hs[i]->nblocks;
+        }
+        g.a.blk_start[n] = tp;
+        g.a.total_blocks = tp;
+        g.blocks = tp;
         memset(&g.a16, 0, sizeof(g.a16));
         memset(&g.am, 0, sizeof(g.am));
         int t16 = 0, tm = 0, nm = 0;
@@ -593,6 +610,13 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
         F.share = reinterpret_cast<double *>(w + L.fs_share);
         F.u = reinterpret_cast<double *>(w + L.fs_u);
         F.lost = reinterpret_cast<double *>(w + L.fs + sizeof(FsDev));
+        const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4);
+        for (int c = 0; c < 2; ++c) {
+            char *base = w + L.fs_hot + c * (2 * rows4 + 256);
+            F.hlist[c] = reinterpret_cast<uint32_t *>(base);
+            F.hpos[c] = reinterpret_cast<uint32_t *>(base + rows4);
+            F.hcount[c] = reinterpret_cast<uint32_t *>(base + 2 * rows4);
+        }
         D.fs = w + L.fs;
     }
     D.partials = reinterpret_cast<double *>(w + L.partials);

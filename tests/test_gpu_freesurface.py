@@ -115,6 +115,27 @@ def test_surface_tension_drop_f64():
     _compare(q, [60, 200], name="3D drop with surface tension 14x12x18")
 
 
+def test_interface_rows_beyond_the_launch_prefix_f64():
+    """The stream/collide pass takes the rows (256 cells) listed as holding
+    interface cells first, in a prefix of 1/32 of the rows and at least 64;
+    listed rows beyond the prefix are processed by their own row blocks.  A
+    wavy surface puts interface cells in most of the 480 rows of this box, so
+    both paths run; the result is the oracle's, class for class."""
+    from paper_0912_4230_amd.sim import Simulation
+    shape = (64, 40, 48)
+    p = I.falling_drop(shape=shape, radius=0.0, G=2e-4, tau=0.8, axis=1)
+    z, y, x = np.meshgrid(np.arange(shape[2]), np.arange(shape[1]), np.arange(shape[0]), indexing="ij")
+    h = 20.0 + 6.0 * np.sin(2 * np.pi * x / 16.0) * np.cos(2 * np.pi * z / 12.0)
+    p.c0 = np.clip(h - y, 0.0, 1.0)
+    sim = Simulation(p, storage="f64")
+    sim.step(1)
+    cls = sim.free_surface()[0].cpu().numpy().reshape(-1)
+    rows_with_if = int((cls.reshape(-1, 256) == IF).any(axis=1).sum())
+    sim.close()
+    assert rows_with_if > 64, rows_with_if
+    _compare(p, [1, 25, 80], diag_every=11, name=f"wavy surface 64x40x48 ({rows_with_if} of 480 rows)")
+
+
 def test_full_tensor_medium_f64():
     shape = (16, 13, 15)
     p = I.falling_drop(shape=shape, radius=4.0, centre=(8.0, 6.5, 9.0), G=4e-4, tau=0.9, axis=2)
