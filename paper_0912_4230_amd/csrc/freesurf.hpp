@@ -121,6 +121,17 @@ __device__ inline void load_cell(const void *P, const void *M, uint32_t n, uint3
     }
 }
 
+// population q of cell idx of one copy, decoded as load_cell does
+template <class S>
+__device__ inline typename Codec<S>::R load_pop(const void *P, const void *M, uint32_t n, uint32_t idx, int q)
+{
+    using R = typename Codec<S>::R;
+    if constexpr (Codec<S>::split)
+        return fma(weight<R>(q), ldg<R>(M, idx), Codec<S>::load(at(plane<S>(P, n, q), idx)));
+    else
+        return Codec<S>::load(at(plane<S>(P, n, q), idx));
+}
+
 // equilibrium deviations f^eq - w at (rho, u) (Eqs. equilc1/2 without the
 // surface-tension part): the collision with omega = 1 and no force of zeros
 template <class R>
@@ -179,17 +190,18 @@ __device__ inline double fs_lambda(const FsDev *F, int c, uint32_t j, int src)
 // of Eq. macros taken over the fill fraction, F = Sum lambda(x + v_q) v_q (a
 // solid neighbour takes lambda(x)); interface cells store m and rho and flag
 // FILL / EMPTY.
-// Waves per SIMD the stream/collide pass is compiled for.  The 16-bit forms
-// without tensor or surface tension take 5 (FP16 deviations) or 6 waves and
-// spill 40-52 bytes per lane (in the BF16 form all spill code sits in the
-// interface branch, which holds three sets of 19 populations); on the 256^3
-// penetration step they are 13% faster than at their natural 4-5 waves.  FP32
-// at 6 waves is 2-4% slower; every other form keeps the compiler's choice.
+// Waves per SIMD the stream/collide pass is compiled for.  Without tensor or
+// surface tension: FP32 and the 16-bit forms take 6 waves (FP32 and BF16 in
+// 80 VGPRs, FP32 without spills, the 16-bit forms with 8-16 bytes of spill
+// per lane), FP16 deviations 5.  On the 256^3 penetration step FP32 runs 5%
+// faster than at its natural 5 waves, the 16-bit forms 13% faster than at 4-5.
+// Every other form keeps the compiler's choice.
 template <class S, bool FT, bool ST> struct FsWaves { static constexpr int value = 1; };
 template <> struct FsWaves<bf16_t, false, false> { static constexpr int value = 6; };
 template <> struct FsWaves<bf16s_t, false, false> { static constexpr int value = 6; };
 template <> struct FsWaves<f16s_t, false, false> { static constexpr int value = 6; };
 template <> struct FsWaves<f16_t, false, false> { static constexpr int value = 5; };
+template <> struct FsWaves<float, false, false> { static constexpr int value = 6; };
 
 //
 // Launch order: a lattice's blocks are a prefix of `cap` blocks followed by one
@@ -246,20 +258,36 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
         const R ie = rcp(eps);
         double m = 0.0;
         if (cls == FS_IF) {
-            R o[NQ];
-            load_cell<S>(L->f[src], L->fm[src], L->pstride, idx, o);
-            R odr = 0, ojx = 0, ojy = 0, ojz = 0;
-            moments_acc<R>(o, odr, ojx, ojy, ojz);
-            const R iro = rcp(R(1) + odr);
-            const R ou[3] = {ojx * iro, ojy * iro, ojz * iro};
-            R eA[NQ];
-            equilibrium<R>(R(1), ou, ie, eA);
+            // velocity of the cell's own post-collision populations; they are
+            // read again link by link below (cache hits) rather than held
+            R ou[3];
+            {
+                R o[NQ];
+                load_cell<S>(L->f[src], L->fm[src], L->pstride, idx, o);
+                R odr = 0, ojx = 0, ojy = 0, ojz = 0;
+                moments_acc<R>(o, odr, ojx, ojy, ojz);
+                const R iro = rcp(R(1) + odr);
+                ou[0] = ojx * iro;
+                ou[1] = ojy * iro;
+                ou[2] = ojz * iro;
+            }
+            // the rebuilt population needs f^eq_q + f^eq_opp(q) only: 9
+            // distinct sums (addition commutes exactly), so the 19
+            // equilibria die here
+            R es[NQ];
+            {
+                R eA[NQ];
+                equilibrium<R>(R(1), ou, ie, eA);
+#pragma unroll
+                for (int q = 1; q < NQ; ++q) es[q] = eA[q] + eA[opp(q)];
+            }
             const double lx = ldg<double>(F->lam[src], idx);
             double dm = 0.0;
             for_groups([&](auto gc) {
                 constexpr int Q0 = decltype(gc)::value;
                 int cn[FS_GROUP];
                 double ln[FS_GROUP];
+                R oo[FS_GROUP];
                 // the neighbours x - v_Q, whose population Q streams in and to
                 // which the population opp(Q) of this cell streams out
                 for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
@@ -267,14 +295,15 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
                     const uint32_t j = shifted<Q, -1>(b);
                     cn[Q - Q0] = ldg<uint8_t>(F->cls, j);
                     ln[Q - Q0] = ldg<double>(F->lam[src], j);
+                    oo[Q - Q0] = load_pop<S>(L->f[src], L->fm[src], L->pstride, idx, opp(Q));
                 });
                 for_range<Q0, Q0 + FS_GROUP>([&](auto qc) {
                     constexpr int Q = decltype(qc)::value;
                     const int cj = shifted_solid<Q, -1>(b) ? FS_SOLID : cn[Q - Q0];
                     if (cj == FS_GAS) {
-                        d[Q] = eA[Q] + eA[opp(Q)] - o[opp(Q)];
+                        d[Q] = es[Q] - oo[Q - Q0];
                     } else if (cj != FS_SOLID) {
-                        const double fl = double(d[Q]) - double(o[opp(Q)]);
+                        const double fl = double(d[Q]) - double(oo[Q - Q0]);
                         dm += cj == FS_LIQ ? fl : fl * (0.5 * (lx + ln[Q - Q0]));
                     }
                 });
