@@ -29,6 +29,17 @@ def problem(physics: str, n: int):
         return I.poiseuille(shape=(n, n, n))
     if physics == "freesurface":
         return I.penetration(shape=(n, n, n), seed=0)
+    if physics == "species":
+        # the miscible workload with a second solute (tau_d 0.8, inlet 0.5)
+        import numpy as np
+        p = I.miscible(shape=(n, n, n), seed=0)
+        p.species_tau_d = (0.8,)
+        p.faces[0].conc_x = (0.5,)
+        p.faces[1].conc_x = (0.0,)
+        p.c0 = np.zeros((2, n, n, n))
+        return p
+    if physics == "wood":
+        return I.wood(shape=(n, n, n))
     raise ValueError(physics)
 
 
@@ -63,7 +74,7 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
     s = sub.add_parser("step")
-    s.add_argument("--physics", default="miscible", choices=["single", "miscible", "immiscible", "freesurface"])
+    s.add_argument("--physics", default="miscible", choices=["single", "miscible", "immiscible", "freesurface", "species", "wood"])
     s.add_argument("--size", type=int, default=256)
     s.add_argument("--storage", default="f32", choices=["f64", "f32", "bf16", "f16", "bf16s", "f16s"])
     s.add_argument("--steps", type=int, default=10)
