@@ -39,12 +39,20 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 // followed by 512 bytes of padding: the 38 read and 38 write streams of a
 // step then do not all sit at the same offset modulo a power-of-two plane
 // size.  Measured against unpadded planes: FP32 256^3 -2%, 512^3 -7%; 16-bit
-// -4 to -7% (256, 768, 1024 and 2048 bytes measured no better).
+// -4 to -7% (256, 768, 1024 and 2048 bytes measured no better).  Planes of a
+// whole number of MiB and at least 256 MiB (512^3 in FP32 and 16 bits) take
+// 512 KiB more: with the 512-byte stagger alone their streams still crowd
+// the same HBM channels (512^3, two runs each: BF16 5.52 -> 4.38-4.57 ms,
+// FP16 5.49 -> 4.49, FP32 8.29 -> 8.03, split forms unchanged), while at
+// 256^3 (64 MiB planes) the larger pad measured 12% slower in FP32.
 size_t plane_stride(const lbm_desc *d)
 {
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     const size_t sb = storage_bytes(d->storage), per = 256 / sb;
-    return (n + per - 1) / per * per + 512 / sb;
+    const size_t base = (n + per - 1) / per * per, bytes = base * sb;
+    const size_t MiB = size_t(1) << 20;
+    const size_t pad = (bytes >= 256 * MiB && bytes % MiB == 0) ? 512 * 1024 + 512 : 512;
+    return base + pad / sb;
 }
 
 struct Layout {
