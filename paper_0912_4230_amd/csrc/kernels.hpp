@@ -748,10 +748,10 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 // first with the same V' (a runtime count per lattice, possibly 0).
 // Waves per SIMD the step is compiled for.  The miscible step with 16-bit
 // storage (diagonal K, one solute) fits in 95-96 VGPRs at 5 waves without
-// spills and runs 5-18% faster there at 256^3 (at exactly 512^3 the
-// deviation forms lose 3-10%); every other form keeps the compiler's own
-// choice (1 = no constraint; the FP32 and FP64 code is the same as without
-// the attribute) and the LDS reserve that holds it at 4 waves.
+// spills and runs 5-18% faster there at 256^3 and 7-9% at 512^3; every other
+// form keeps the compiler's own choice (1 = no constraint; the FP32 and FP64
+// code is the same as without the attribute) and the LDS reserve that holds
+// it at 4 waves.
 template <int PHYS, class S, bool FT, bool MS> struct StepWaves { static constexpr int value = 1; };
 template <> struct StepWaves<PH_MISCIBLE, bf16_t, false, false> { static constexpr int value = 5; };
 template <> struct StepWaves<PH_MISCIBLE, f16_t, false, false> { static constexpr int value = 5; };
