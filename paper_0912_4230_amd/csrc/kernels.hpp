@@ -126,6 +126,22 @@ __device__ inline int xcd_remap(int b, int nb)
 // 256^3 FP32 miscible step from 1.07x to 1.03x of the algorithmic reads but
 // measures 4% slower than the identity, so it is compiled in only with
 // PLBM_SLAB=1.  bpp == 0: identity.
+// Hardware block b (dispatched round-robin, XCD b mod 8) -> logical block:
+// each XCD takes runs of XCD_ROWS consecutive rows (blocks), so that most
+// y-neighbour rows of a block's stencils were fetched into the same XCD's L2,
+// while the eight XCDs still work on 8 x XCD_ROWS consecutive rows at a time.
+// Identity unless the lattice's block count is a multiple of 8 x XCD_ROWS.
+// Measured against the identity (results bitwise the same): 256^3 FP32 -0.3
+// to -1.2%, BF16 -1.5%; 512^3 FP32 -1.7%, BF16 -4%, FP16 split -9%.  Runs of
+// 2 rows gained less, runs of 8 cost the 256^3 FP32 step 1.6%.
+constexpr int XCD_ROWS = 4;
+__device__ inline int row_group_remap(int b, int nb)
+{
+    if (nb % (8 * XCD_ROWS) != 0) return b;
+    const int x = b & 7, s = b >> 3;
+    return (s / XCD_ROWS) * (8 * XCD_ROWS) + x * XCD_ROWS + (s % XCD_ROWS);
+}
+
 __device__ inline int slab_remap(int b, int bpp)
 {
     if (bpp == 0) return b;
@@ -766,7 +782,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
     const int gb = xcd_remap(blockIdx.x, a.total_blocks);
     const int l = find_lattice(a, gb);
     const LatDev *__restrict__ L = a.lat[l];
-    const int lb = slab_remap(gb - a.blk_start[l], L->bpp);
+    const int lb = row_group_remap(slab_remap(gb - a.blk_start[l], L->bpp), a.blk_start[l + 1] - a.blk_start[l]);
     const int flags = a.flags[l];
     const int src = flags & 1;
     const bool mom = (flags & 2) != 0;
@@ -994,7 +1010,7 @@ __global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
     const int gb = xcd_remap(blockIdx.x, a.total_blocks);
     const int l = find_lattice(a, gb);
     const LatDev *__restrict__ L = a.lat[l];
-    const int lb = slab_remap(gb - a.blk_start[l], L->bpp);
+    const int lb = row_group_remap(slab_remap(gb - a.blk_start[l], L->bpp), a.blk_start[l + 1] - a.blk_start[l]);
     const int src = a.flags[l] & 1;
     const uint32_t ncell = L->ncell;
     const uint32_t idx = uint32_t(lb) * BLOCK + threadIdx.x;
