@@ -234,7 +234,11 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes,
  * fields of every non-solid cell on the device (eps in (0,1], K^-1 >= 0,
  * rho0 > 0, all finite) and returns LBM_EINVAL if a value is out of range,
  * or if m->solid is set on a handle created without solid_mask.  Resets the
- * step count.  Synchronises the handle's stream. */
+ * step count.  Synchronises the handle's stream.  The uniform values and the
+ * mask flag are checked on the host first: such a rejection leaves the
+ * handle untouched (a ready handle stays ready with its medium).  A
+ * rejection by the device checks, or a device error, leaves the handle not
+ * ready (lbm_step returns LBM_ESTATE) until a later call succeeds. */
 lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m);
 
 /* Advance nsteps >= 0 time steps, asynchronously on the handle's stream. */
@@ -274,13 +278,15 @@ lbm_status lbm_populations(lbm_t h, int lattice, void *dst);
 lbm_status lbm_solute_totals(lbm_t h, double *totals);
 
 /* Free surface (Sec. 3): the cell classes after the last step (ncell bytes:
- * 0 gas, 1 interface, 2 liquid, 3 solid) and the liquid mass per cell
- * (ncell doubles: m for interface cells, rho for liquid cells, 0 for gas and
- * solid), into caller device buffers (each may be NULL), and into *lost (host,
- * may be NULL) the excess mass that found no interface cell to take it since
- * lbm_set_medium.  LBM_EINVAL for a handle of another physics.  Synchronises
- * the stream. */
-lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lost);
+ * 0 gas, 1 interface, 2 liquid, 3 solid), the liquid mass per cell (ncell
+ * doubles: m for interface cells, rho for liquid cells, 0 for gas and
+ * solid) and the fill fraction per cell (ncell doubles: lambda = m / rho of
+ * interface cells as the last step stored it, 1 for liquid cells, 0 for gas
+ * and solid), into caller device buffers (each may be NULL), and into *lost
+ * (host, may be NULL) the excess mass that found no interface cell to take
+ * it since lbm_set_medium.  LBM_EINVAL for a handle of another physics.
+ * Synchronises the stream. */
+lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lambda, double *lost);
 
 /* Completed steps since lbm_set_medium, or -1 for a NULL handle. */
 long long lbm_steps_done(lbm_t h);

@@ -1373,3 +1373,28 @@ double orc_fs_state(const orc_state *s, unsigned char *cls, double *mass)
     }
     return s->fs_lost;
 }
+
+/* free surface: replace the cell classes (0 gas, 1 interface, 2 liquid; the
+ * entries of non-fluid cells are ignored), the liquid masses m and the fill
+ * fractions lambda of the current state, to continue from a state exported
+ * elsewhere (the populations are replaced with orc_set_state).  Gas cells
+ * get zero populations and moments, as this file's own steps leave them.
+ * Returns -1 for the other physics.                                        */
+int orc_fs_set_state(orc_state *s, const unsigned char *cls, const double *mass, const double *lam)
+{
+    if (s->p.physics != PHYS_FREESURF) return -1;
+    long n = s->n;
+    for (long i = 0; i < n; ++i) {
+        if (s->type[i] != CELL_FLUID) continue;
+        s->fst[i] = cls[i];
+        s->mass[i] = mass[i];
+        s->lam[i] = lam[i];
+        s->conc[i] = lam[i];
+        if (cls[i] == FS_GAS) {
+            for (int q = 0; q < NQ; ++q) s->f[s->cur][(long)q * n + i] = 0.0;
+            s->rho[i] = 0.0;
+            for (int a = 0; a < 3; ++a) s->vel[a * n + i] = 0.0;
+        }
+    }
+    return 0;
+}

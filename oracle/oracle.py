@@ -7,6 +7,7 @@ description from the seeded input module.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -44,41 +45,60 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from oracle import build_oracle
             build_oracle.build()
-        L = C.CDLL(LIB_PATH)
-        dp = C.POINTER(C.c_double)
-        L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.POINTER(OrcParams), dp, dp, dp, dp, dp, C.POINTER(C.c_ubyte)]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_step.argtypes = [C.c_void_p, C.c_int]
-        L.orc_step.restype = C.c_int
-        L.orc_steps_done.argtypes = [C.c_void_p]
-        L.orc_steps_done.restype = C.c_long
-        L.orc_moments.argtypes = [C.c_void_p, dp, dp, dp]
-        L.orc_diag.argtypes = [C.c_void_p, dp]
-        L.orc_get_state.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_set_state.argtypes = [C.c_void_p, C.c_int, dp, C.c_long]
-        L.orc_step_cells.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_long), dp, dp, dp]
-        L.orc_cell_types.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte)]
-        L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
-        L.orc_feq.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, dp, dp]
-        L.orc_force.argtypes = [C.c_double, dp, C.c_double, C.c_double, dp, dp]
-        L.orc_heq.argtypes = [C.c_double, dp, dp]
-        L.orc_viscosity.argtypes = [C.POINTER(OrcParams), C.c_double, C.c_double]
-        L.orc_viscosity.restype = C.c_double
-        L.orc_solve_speed.argtypes = [dp, dp, dp]
-        L.orc_solve_speed.restype = C.c_double
-        L.orc_porous_velocity.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
-        L.orc_porous_velocity_full.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
-        L.orc_sym_sqrt.argtypes = [dp, dp]
-        L.orc_set_threads.argtypes = [C.c_int]
-        L.orc_fs_state.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte), dp]
-        L.orc_fs_state.restype = C.c_double
-        L.orc_species_conc.argtypes = [C.c_void_p, C.c_int, dp]
-        L.orc_species_conc.restype = C.c_int
-        L.orc_species_totals.argtypes = [C.c_void_p, dp]
-        L.orc_species_totals.restype = C.c_int
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def library(path: str):
+    """Run the oracle from another build of lbm_oracle.c (for example a copy
+    with a planted mistake, to show that a pin fails on it) inside the block."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def _load(path: str):
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.POINTER(OrcParams), dp, dp, dp, dp, dp, C.POINTER(C.c_ubyte)]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int]
+    L.orc_step.restype = C.c_int
+    L.orc_steps_done.argtypes = [C.c_void_p]
+    L.orc_steps_done.restype = C.c_long
+    L.orc_moments.argtypes = [C.c_void_p, dp, dp, dp]
+    L.orc_diag.argtypes = [C.c_void_p, dp]
+    L.orc_get_state.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_set_state.argtypes = [C.c_void_p, C.c_int, dp, C.c_long]
+    L.orc_step_cells.argtypes = [C.c_void_p, C.c_long, C.POINTER(C.c_long), dp, dp, dp]
+    L.orc_cell_types.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte)]
+    L.orc_lattice.argtypes = [C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
+    L.orc_feq.argtypes = [C.c_double, dp, C.c_double, C.c_double, C.c_double, dp, dp]
+    L.orc_force.argtypes = [C.c_double, dp, C.c_double, C.c_double, dp, dp]
+    L.orc_heq.argtypes = [C.c_double, dp, dp]
+    L.orc_viscosity.argtypes = [C.POINTER(OrcParams), C.c_double, C.c_double]
+    L.orc_viscosity.restype = C.c_double
+    L.orc_solve_speed.argtypes = [dp, dp, dp]
+    L.orc_solve_speed.restype = C.c_double
+    L.orc_porous_velocity.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
+    L.orc_porous_velocity_full.argtypes = [C.POINTER(OrcParams), C.c_double, dp, C.c_double, dp, dp, dp]
+    L.orc_sym_sqrt.argtypes = [dp, dp]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_fs_state.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte), dp]
+    L.orc_fs_state.restype = C.c_double
+    L.orc_species_conc.argtypes = [C.c_void_p, C.c_int, dp]
+    L.orc_species_conc.restype = C.c_int
+    L.orc_species_totals.argtypes = [C.c_void_p, dp]
+    L.orc_species_totals.restype = C.c_int
+    L.orc_fs_set_state.argtypes = [C.c_void_p, C.POINTER(C.c_ubyte), dp, dp]
+    L.orc_fs_set_state.restype = C.c_int
+    return L
 
 
 def _dp(a: np.ndarray):
@@ -246,6 +266,17 @@ class Oracle:
         lost = lib().orc_fs_state(self.h, cls, _dp(m))
         return (np.frombuffer(cls, dtype=np.uint8).copy().reshape(nz, ny, nx),
                 m.reshape(nz, ny, nx), lost)
+
+    def fs_set_state(self, cls, mass, lam):
+        """Free surface: replace the classes (0 gas, 1 interface, 2 liquid),
+        liquid masses and fill fractions of the current state (arrays of
+        ncell values; the populations are replaced with set_state)."""
+        c = np.ascontiguousarray(np.asarray(cls).reshape(-1), dtype=np.uint8)
+        m = _vec(mass).reshape(-1)
+        lm = _vec(lam).reshape(-1)
+        assert c.size == m.size == lm.size == self.n
+        if lib().orc_fs_set_state(self.h, c.ctypes.data_as(C.POINTER(C.c_ubyte)), _dp(m), _dp(lm)) != 0:
+            raise ValueError("not a free-surface problem")
 
     def species_conc(self, k: int):
         """Concentration of solute k (0: the first) of the last step, (nz,ny,nx)."""

@@ -97,7 +97,7 @@ def lib():
         L.lbm_solute_totals.restype = C.c_int
         L.lbm_solute_totals.argtypes = [vp, C.POINTER(C.c_double)]
         L.lbm_free_surface.restype = C.c_int
-        L.lbm_free_surface.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
+        L.lbm_free_surface.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_strerror.argtypes = [C.c_int]
         _lib = L
@@ -157,12 +157,12 @@ def lbm_solute_totals(h, nspecies: int):
     return [float(out[k]) for k in range(nspecies)]
 
 
-def lbm_free_surface(h, cls_ptr: int = 0, mass_ptr: int = 0) -> float:
-    """Free surface: classes (uint8) and masses (double) into device buffers
-    (0: skip); returns the lost excess mass."""
+def lbm_free_surface(h, cls_ptr: int = 0, mass_ptr: int = 0, lambda_ptr: int = 0) -> float:
+    """Free surface: classes (uint8), masses and fill fractions (double) into
+    device buffers (0: skip); returns the lost excess mass."""
     lost = C.c_double(0.0)
-    _check(lib().lbm_free_surface(h, C.c_void_p(cls_ptr or None), C.c_void_p(mass_ptr or None), C.byref(lost)),
-           "lbm_free_surface")
+    _check(lib().lbm_free_surface(h, C.c_void_p(cls_ptr or None), C.c_void_p(mass_ptr or None),
+                                  C.c_void_p(lambda_ptr or None), C.byref(lost)), "lbm_free_surface")
     return float(lost.value)
 
 

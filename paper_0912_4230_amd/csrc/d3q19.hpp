@@ -38,6 +38,20 @@ __host__ __device__ constexpr R weight(int q)
     return q == 0 ? R(1) / R(3) : (q <= 6 ? R(1) / R(18) : R(1) / R(36));
 }
 
+// FP32 weights whose exact sum is 1.  The rounded 1/3, 1/18 and 1/36 sum to
+// 1 + 1.49e-8, so every collision returned 1 + 1.49e-8 omega times the
+// equilibrium mass of the cell: a bias that accumulates step after step (the
+// FP32 solute mass of a closed box grew by 2.3e-8 per step at tau_d = 0.65).
+// Here w_2 = 14913080 * 2^-29 (1/36 to 6e-8; its mantissa is even), w_1 = 2 w_2
+// and w_0 = 1 - 24 w_2 = 11184812 * 2^-25, all exact in FP32, so that
+// w_0 + 6 w_1 + 12 w_2 = 1 exactly.  The isotropy sums (Sum w v_a v_b = 1/3)
+// then hold to 6e-8, below FP32 resolution.
+template <>
+__host__ __device__ constexpr float weight<float>(int q)
+{
+    return q == 0 ? 11184812.0f / 33554432.0f : (q <= 6 ? 29826160.0f / 536870912.0f : 14913080.0f / 536870912.0f);
+}
+
 // ---------------------------------------------------------------------------
 // storage codecs: Codec<S>::R is the compute type, load/store convert.
 // Populations are streamed: each value is read once, one step after it was

@@ -158,7 +158,9 @@ __device__ inline FsCell fs_cell(const BatchArgs &a)
     c.l = find_lattice(a, gb);
     c.L = a.lat[c.l];
     c.F = fs_of(c.L);
-    c.lb = slab_remap(gb - a.blk_start[c.l], c.L->bpp);
+    // the pass-1 grid of a lattice (listed-row prefix + one block per row) is
+    // not a whole number of planes: no slab or row-group remapping here
+    c.lb = gb - a.blk_start[c.l];
     c.flags = a.flags[c.l];
     c.ncell = c.L->ncell;
     c.idx = uint32_t(c.lb) * BLOCK + threadIdx.x;
@@ -218,6 +220,7 @@ template <class S, bool FT, bool ST = false>
 __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>::value))) void k_fs_step(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
+    [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     FsCell c = fs_cell(a);
     const LatDev *__restrict__ L = c.L;
     const FsDev *__restrict__ F = c.F;
@@ -255,7 +258,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
         const Nbr b = neighbours(L, x, y, z, lw);
         pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
         const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
-        const R ie = rcp(eps);
+        const R ie = rcp<HW>(eps);
         double m = 0.0;
         if (cls == FS_IF) {
             // velocity of the cell's own post-collision populations; they are
@@ -266,7 +269,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
                 load_cell<S>(L->f[src], L->fm[src], L->pstride, idx, o);
                 R odr = 0, ojx = 0, ojy = 0, ojz = 0;
                 moments_acc<R>(o, odr, ojx, ojy, ojz);
-                const R iro = rcp(R(1) + odr);
+                const R iro = rcp<HW>(R(1) + odr);
                 ou[0] = ojx * iro;
                 ou[1] = ojy * iro;
                 ou[2] = ojz * iro;
@@ -314,17 +317,17 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
         R drho = 0, jx = 0, jy = 0, jz = 0;
         moments_acc<R>(d, drho, jx, jy, jz);
         const R rho = R(1) + drho;
-        const R irho = rcp(rho);
+        const R irho = rcp<HW>(rho);
         const R V[3] = {jx * irho, jy * irho, jz * irho};
-        const R nu = nuc * fexp(R(L->k0));
-        const R omega = rcp(R(0.5) + R(3) * nu);
+        const R nu = nuc * fexp<HW>(R(L->k0));
+        const R omega = rcp<HW>(R(0.5) + R(3) * nu);
         R u[3], Fx[3];
         if constexpr (FT) {
             const R q[4] = {ldg<R>(L->kinv, idx), ldp<R>(L->kinv, ncell, 1, idx), ldp<R>(L->kinv, ncell, 2, idx),
                             ldp<R>(L->kinv, ncell, 3, idx)};
             const R mu[3] = {ldp<R>(L->kinv, ncell, 4, idx), ldp<R>(L->kinv, ncell, 5, idx),
                              ldp<R>(L->kinv, ncell, 6, idx)};
-            porous_force_frame<R>(L, eps, q, mu, nu, V, u, Fx);
+            porous_force_frame<R, HW>(L, eps, q, mu, nu, V, u, Fx);
         } else {
             R kinv[3];
             if (L->uniform_kinv) {
@@ -336,7 +339,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
                 kinv[1] = ldp<R>(L->kinv, ncell, 1, idx);
                 kinv[2] = ldp<R>(L->kinv, ncell, 2, idx);
             }
-            porous_force<R>(L, eps, kinv, nu, V, u, Fx);
+            porous_force<R, HW>(L, eps, kinv, nu, V, u, Fx);
         }
         R Fs[3] = {0, 0, 0}, Fn = 0, iFn = 0, st = 0;
         if constexpr (ST) {
@@ -369,7 +372,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
                 });
                 for (int c = 0; c < 3; ++c) Fs[c] = R(g[c]);
                 Fn = sqrt(Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2]);
-                iFn = Fn > R(0) ? rcp(Fn) : R(0);
+                iFn = Fn > R(0) ? rcp<HW>(Fn) : R(0);
                 st = Fn > R(0) ? R(L->A) * eps * (R(0.5) + R(3) * nu) : R(0);
             }
         }
@@ -500,6 +503,7 @@ template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
+    [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsTile t = fs_tile(a);
     if (t.base >= t.ncell) return;
     const LatDev *__restrict__ L = t.L;
@@ -543,7 +547,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
             const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
             const R ur[3] = {R(ua[0]), R(ua[1]), R(ua[2])};
             R e[NQ];
-            equilibrium<R>(R(ra), ur, rcp(eps), e);
+            equilibrium<R>(R(ra), ur, rcp<HW>(eps), e);
             store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, e);
             stg<double>(F->mass, idx, 0.0);
             stg<double>(F->rho, idx, ra);
@@ -611,6 +615,7 @@ template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
+    [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsTile t = fs_tile(a);
     if (t.base >= t.ncell) return;
     const LatDev *__restrict__ L = t.L;
@@ -674,6 +679,7 @@ template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fs_moments(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
+    [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsCell c = fs_cell(a);
     const LatDev *__restrict__ L = c.L;
     const FsDev *__restrict__ F = c.F;
@@ -779,12 +785,16 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const 
     block_reduce_store(part, L->partials + size_t(blockIdx.x) * NPART);
 }
 
-// classes and masses for lbm_free_surface: m of interface cells, rho (from
-// the current populations) of liquid cells, 0 elsewhere
+// classes, masses and fill fractions for lbm_free_surface: m of interface
+// cells, rho (from the current populations) of liquid cells, 0 elsewhere;
+// lambda = m / rho of interface cells as the step stored it, 1 for liquid
+// cells, 0 elsewhere
 template <class S>
-__global__ __launch_bounds__(BLOCK) void k_fs_export(const LatDev *L, int src, unsigned char *cls, double *mass)
+__global__ __launch_bounds__(BLOCK) void k_fs_export(const LatDev *L, int src, unsigned char *cls, double *mass,
+                                                     double *lam)
 {
     using R = typename Codec<S>::R;
+    [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= uint32_t(L->ncell)) return;
     const FsDev *F = fs_of(L);
@@ -804,6 +814,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_export(const LatDev *L, int src, u
         }
         mass[idx] = m;
     }
+    if (lam) lam[idx] = c == FS_IF ? ldg<double>(F->lam[src], idx) : (c == FS_LIQ ? 1.0 : 0.0);
 }
 
 }  // namespace plbm

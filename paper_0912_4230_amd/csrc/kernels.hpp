@@ -117,6 +117,27 @@ __device__ inline int xcd_remap(int b, int nb)
     return xcd * q + min(xcd, r) + slot;
 }
 
+// Hardware block b (dispatched round-robin, XCD b mod 8) -> logical block of
+// its lattice: each XCD takes runs of XCD_ROWS consecutive rows (blocks), so
+// that most y-neighbour rows of a block's stencils were fetched into the same
+// XCD's L2, while the eight XCDs still work on 8 x XCD_ROWS consecutive rows at
+// a time.  b is the block's index within its lattice's range of the launch;
+// every range starts at a multiple of 8 x XCD_ROWS and spans a whole number of
+// such groups (the library pads it; blocks mapped beyond the lattice's rows
+// exit), so b mod 8 is the XCD in batched launches too.  Measured against the
+// identity (results bitwise the same): 256^3 FP32 -0.3 to -1.2%, BF16 -1.5%;
+// 512^3 FP32 -1.7%, BF16 -4%, FP16 split -9%.  Runs of 2 rows gained less, runs
+// of 8 cost the 256^3 FP32 step 1.6%.  Identity unless nb is a multiple of
+// 8 x XCD_ROWS.
+constexpr int XCD_ROWS = 4;
+constexpr int XCD_GROUP = 8 * XCD_ROWS;
+__device__ inline int row_group_remap(int b, int nb)
+{
+    if (nb % XCD_GROUP != 0) return b;
+    const int x = b & 7, s = b >> 3;
+    return (s / XCD_ROWS) * XCD_GROUP + x * XCD_ROWS + (s % XCD_ROWS);
+}
+
 // Slab mapping within one lattice: when a z-plane is a whole number bpp of
 // blocks with bpp a multiple of 8, hardware block b (XCD b mod 8) takes the
 // (b mod 8)-th eighth of the y-rows of plane b / bpp.  Each XCD then owns one
@@ -125,28 +146,23 @@ __device__ inline int xcd_remap(int b, int nb)
 // XCDs sweep the same plane together.  It cuts the fetched bytes of the
 // 256^3 FP32 miscible step from 1.07x to 1.03x of the algorithmic reads but
 // measures 4% slower than the identity, so it is compiled in only with
-// PLBM_SLAB=1.  bpp == 0: identity.
-// Hardware block b (dispatched round-robin, XCD b mod 8) -> logical block:
-// each XCD takes runs of XCD_ROWS consecutive rows (blocks), so that most
-// y-neighbour rows of a block's stencils were fetched into the same XCD's L2,
-// while the eight XCDs still work on 8 x XCD_ROWS consecutive rows at a time.
-// Identity unless the lattice's block count is a multiple of 8 x XCD_ROWS.
-// Measured against the identity (results bitwise the same): 256^3 FP32 -0.3
-// to -1.2%, BF16 -1.5%; 512^3 FP32 -1.7%, BF16 -4%, FP16 split -9%.  Runs of
-// 2 rows gained less, runs of 8 cost the 256^3 FP32 step 1.6%.
-constexpr int XCD_ROWS = 4;
-__device__ inline int row_group_remap(int b, int nb)
-{
-    if (nb % (8 * XCD_ROWS) != 0) return b;
-    const int x = b & 7, s = b >> 3;
-    return (s / XCD_ROWS) * (8 * XCD_ROWS) + x * XCD_ROWS + (s % XCD_ROWS);
-}
-
+// PLBM_SLAB=1 (step and colour kernels only).  bpp == 0: identity.
 __device__ inline int slab_remap(int b, int bpp)
 {
     if (bpp == 0) return b;
     const int z = b / bpp, r = b - z * bpp;
     return z * bpp + (r & 7) * (bpp >> 3) + (r >> 3);
+}
+
+// Logical block (row) of the lattice-local hardware block b of a step or
+// colour launch whose range for this lattice is nb blocks; -1 for the padding
+// beyond the lattice's rows.  The slab mapping, when compiled in, replaces the
+// row groups.
+__device__ inline int step_block(int b, int nb, const LatDev *L)
+{
+    if constexpr (PLBM_SLAB) return b < L->nblocks ? slab_remap(b, L->bpp) : -1;
+    const int lb = row_group_remap(b, nb);
+    return lb < L->nblocks ? lb : -1;
 }
 
 __device__ inline int find_lattice(const BatchArgs &a, int gb)
@@ -401,16 +417,49 @@ __device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, con
     }
 }
 
-// reciprocal, square root, reciprocal square root and exponential: the
-// hardware instructions (about 1 ulp) in FP32, the correctly rounded / libm
-// forms in FP64
-__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Reciprocal, square root, reciprocal square root and exponential in two
+// forms: HW = false the correctly rounded division and square root and the
+// libm-accurate exp, HW = true the hardware instructions (about 1 ulp).  FP64
+// is always the accurate form.  HwMath<S>: FP32 storage computes with the
+// accurate forms (free there: the FP32 steps are bound by HBM, 0.945 ms either
+// way at 256^3); the 16-bit storage forms, whose rounding of the stored
+// populations is 4-5 orders larger than an ulp of the arithmetic, keep the
+// hardware forms (the accurate ones cost the BF16 step 4%).
+template <class S> struct HwMath { static constexpr bool value = true; };
+template <> struct HwMath<float> { static constexpr bool value = false; };
+template <> struct HwMath<double> { static constexpr bool value = false; };
+
+template <bool HW>
+__device__ inline float rcp(float x)
+{
+    if constexpr (HW) return __builtin_amdgcn_rcpf(x);
+    else return 1.0f / x;
+}
+template <bool HW>
 __device__ inline double rcp(double x) { return 1.0 / x; }
-__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <bool HW>
+__device__ inline float fsqrt(float x)
+{
+    if constexpr (HW) return __builtin_amdgcn_sqrtf(x);
+    else return sqrtf(x);
+}
+template <bool HW>
 __device__ inline double fsqrt(double x) { return sqrt(x); }
-__device__ inline float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+template <bool HW>
+__device__ inline float frsq(float x)
+{
+    if constexpr (HW) return __builtin_amdgcn_rsqf(x);
+    else return 1.0f / sqrtf(x);
+}
+template <bool HW>
 __device__ inline double frsq(double x) { return 1.0 / sqrt(x); }
-__device__ inline float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+template <bool HW>
+__device__ inline float fexp(float x)
+{
+    if constexpr (HW) return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+    else return expf(x);
+}
+template <bool HW>
 __device__ inline double fexp(double x) { return exp(x); }
 
 // unsigned division by an invariant divisor (Granlund and Montgomery,
@@ -463,10 +512,10 @@ template <> struct Newton<double> { static constexpr double tol = 1e-15; };
 // phi(s) = s - sqrt(sum_a W_a^2 / (lam_a + mu_a s)^2) from the Darcy-only
 // value, an upper bound of the root; stops when the update is below the
 // working precision (at most 8 iterations).
-template <class R>
+template <class R, bool HW>
 __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], const R ilam[3])
 {
-    R s = fsqrt((W[0] * ilam[0]) * (W[0] * ilam[0]) + (W[1] * ilam[1]) * (W[1] * ilam[1]) +
+    R s = fsqrt<HW>((W[0] * ilam[0]) * (W[0] * ilam[0]) + (W[1] * ilam[1]) * (W[1] * ilam[1]) +
                 (W[2] * ilam[2]) * (W[2] * ilam[2]));
     // the root lies in [s / (1 + max mu s / min lam), s]: when that bracket is
     // below the working precision the Darcy value is the answer
@@ -477,7 +526,7 @@ __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], con
             R R2 = 0, dR = 0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const R id = rcp(lam[a] + mu[a] * s);
+                const R id = rcp<HW>(lam[a] + mu[a] * s);
                 const R t = W[a] * id;
                 R2 += t * t;
                 dR += t * t * mu[a] * id;
@@ -621,41 +670,41 @@ __device__ inline void recolour(R *g, const R *d, R C, const R Cw[3], const R rw
 // Porous velocity and force (Eqs. forcement, expandV, expandVsub with eps on
 // G, diagonal K, optional Forchheimer drag).  G is the body force in the
 // frame of kinv.
-template <class R>
+template <class R, bool HW>
 __device__ inline void porous_core(const LatDev *L, const R G[3], R eps, const R kinv[3], R nu, const R V[3],
                                    R u[3], R Fx[3])
 {
     R W[3], lam[3], ilam[3], mu[3], sk[3];
     R Feps = R(0);
     const bool forch = L->forch != 0;
-    if (forch) Feps = R(1.75) * frsq(R(150) * eps * eps * eps);
+    if (forch) Feps = R(1.75) * frsq<HW>(R(150) * eps * eps * eps);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         W[a] = V[a] + R(0.5) * eps * G[a];
         lam[a] = R(1) + R(0.5) * eps * nu * kinv[a];
-        ilam[a] = rcp(lam[a]);
-        sk[a] = forch ? fsqrt(kinv[a]) : R(0);
+        ilam[a] = rcp<HW>(lam[a]);
+        sk[a] = forch ? fsqrt<HW>(kinv[a]) : R(0);
         mu[a] = R(0.5) * eps * Feps * sk[a];
     }
     if (forch) {
-        const R s = solve_speed<R>(W, lam, mu, ilam);
+        const R s = solve_speed<R, HW>(W, lam, mu, ilam);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) u[a] = W[a] * rcp(lam[a] + mu[a] * s);
+        for (int a = 0; a < 3; ++a) u[a] = W[a] * rcp<HW>(lam[a] + mu[a] * s);
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) u[a] = W[a] * ilam[a];
     }
-    const R sp = forch ? fsqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) : R(0);
+    const R sp = forch ? fsqrt<HW>(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) : R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         Fx[a] = eps * G[a] - eps * nu * kinv[a] * u[a] - eps * Feps * sp * sk[a] * u[a];
 }
 
-template <class R>
+template <class R, bool HW>
 __device__ inline void porous_force(const LatDev *L, R eps, const R kinv[3], R nu, const R V[3], R u[3], R Fx[3])
 {
     const R G[3] = {R(L->G[0]), R(L->G[1]), R(L->G[2])};
-    porous_core<R>(L, G, eps, kinv, nu, V, u, Fx);
+    porous_core<R, HW>(L, G, eps, kinv, nu, V, u, Fx);
 }
 
 // Rotation matrix (columns: the eigenvectors of K^-1) of a unit quaternion
@@ -678,7 +727,7 @@ __device__ inline void quat_matrix(const R q[4], R M[3][3])
 // Full tensor K^-1 = Q diag(mu) Q^T: K^-1 and K^-1/2 share the frame Q, so in
 // that frame Eqs. forcement and expandV (with the Forchheimer drag) are the
 // diagonal ones.  V and G are rotated in, V' and F^ext rotated back.
-template <class R>
+template <class R, bool HW>
 __device__ inline void porous_force_frame(const LatDev *L, R eps, const R q[4], const R mu[3], R nu, const R V[3],
                                           R u[3], R Fx[3])
 {
@@ -692,7 +741,7 @@ __device__ inline void porous_force_frame(const LatDev *L, R eps, const R q[4], 
         Gr[a] = M[0][a] * G[0] + M[1][a] * G[1] + M[2][a] * G[2];
     }
     R ur[3], Fr[3];
-    porous_core<R>(L, Gr, eps, mu, nu, Vr, ur, Fr);
+    porous_core<R, HW>(L, Gr, eps, mu, nu, Vr, ur, Fr);
     // F^ext = eps G - Q (drag in the frame); eps G exactly, the drag rotated back
     R Dr[3];
 #pragma unroll
@@ -779,10 +828,12 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
     const BatchArgs a)
 {
     using R = typename Codec<S>::R;
+    constexpr bool HW = HwMath<S>::value;
     const int gb = xcd_remap(blockIdx.x, a.total_blocks);
     const int l = find_lattice(a, gb);
     const LatDev *__restrict__ L = a.lat[l];
-    const int lb = row_group_remap(slab_remap(gb - a.blk_start[l], L->bpp), a.blk_start[l + 1] - a.blk_start[l]);
+    const int lb = step_block(gb - a.blk_start[l], a.blk_start[l + 1] - a.blk_start[l], L);
+    if (lb < 0) return;   // padding of the lattice's block range (uniform over the block)
     const int flags = a.flags[l];
     const int src = flags & 1;
     const bool mom = (flags & 2) != 0;
@@ -825,11 +876,11 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
         R drho = 0, jx = 0, jy = 0, jz = 0;
         moments_acc<R>(d, drho, jx, jy, jz);
         const R rho = R(1) + drho;
-        const R irho = rcp(rho);
+        const R irho = rcp<HW>(rho);
         const R V[3] = {jx * irho, jy * irho, jz * irho};
 
         const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
-        const R ie = rcp(eps);
+        const R ie = rcp<HW>(eps);
 
         R sh = 0, rho1 = 0, C = 0;
         if constexpr (PHYS == PH_MISCIBLE) {
@@ -845,12 +896,12 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
         if constexpr (PHYS == PH_IMMISCIBLE) {
             nu = C * R(L->nu1) + (R(1) - C) * R(L->nu2);
         } else if constexpr (PHYS == PH_MISCIBLE) {
-            nu = nuc * fexp(R(L->k1) * C + R(L->k0));
+            nu = nuc * fexp<HW>(R(L->k1) * C + R(L->k0));
         } else {
-            nu = nuc * fexp(R(L->k0));
+            nu = nuc * fexp<HW>(R(L->k0));
         }
         const R tau = R(0.5) + R(3) * nu;
-        const R omega = rcp(tau);
+        const R omega = rcp<HW>(tau);
 
         R u[3], Fx[3];
         if constexpr (FT) {
@@ -858,7 +909,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
                             ldp<R>(L->kinv, ncell, 3, idx)};
             const R mu[3] = {ldp<R>(L->kinv, ncell, 4, idx), ldp<R>(L->kinv, ncell, 5, idx),
                              ldp<R>(L->kinv, ncell, 6, idx)};
-            porous_force_frame<R>(L, eps, q, mu, nu, V, u, Fx);
+            porous_force_frame<R, HW>(L, eps, q, mu, nu, V, u, Fx);
         } else {
             R kinv[3];
             if (L->uniform_kinv) {
@@ -870,7 +921,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
                 kinv[1] = ldp<R>(L->kinv, ncell, 1, idx);
                 kinv[2] = ldp<R>(L->kinv, ncell, 2, idx);
             }
-            porous_force<R>(L, eps, kinv, nu, V, u, Fx);
+            porous_force<R, HW>(L, eps, kinv, nu, V, u, Fx);
         }
 
         R F[3] = {0, 0, 0};
@@ -878,7 +929,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
         if constexpr (PHYS == PH_IMMISCIBLE) {
             colour_acc<R>(L->rho1, b, F[0], F[1], F[2]);
             Fn = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
-            iFn = Fn > R(0) ? rcp(Fn) : R(0);
+            iFn = Fn > R(0) ? rcp<HW>(Fn) : R(0);
             st = Fn > R(0) ? R(L->A) * eps * tau : R(0);
         }
         const Coll<R> cl = make_coll<R>(drho, rho, omega, ie, u, Fx, st, F, Fn, iFn);
@@ -935,14 +986,16 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
     } else if (type == CELL_RES) {
         // the fixed reservoir state, as set up: f^eq(rho_bc, V' = 0) and
         // h^eq(eps C_bc, 0) or g = C_bc f
-        const R rb = R(L->face_rho[face]), cb = R(L->face_conc[face]);
+        // rho_bc - 1 is formed in double before rounding (1 + 3 x 0.0441 in
+        // FP32 minus 1 would carry the FP32 error of 1.1323, 1.5e-7 of drho)
+        const R rb = R(L->face_rho[face]), cb = R(L->face_conc[face]), drb = R(L->face_rho[face] - 1.0);
         R eps = R(1);
         if constexpr (PHYS == PH_MISCIBLE) eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
         if constexpr (MS) x_eps = eps;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const R w = weight<R>(q);
-            d[q] = w * (rb - R(1));
+            d[q] = w * drb;
             hq[q] = PHYS == PH_MISCIBLE ? w * eps * cb : (PHYS == PH_IMMISCIBLE ? cb * w * rb : R(0));
         }
     } else {
@@ -1010,7 +1063,8 @@ __global__ __launch_bounds__(BLOCK) void k_colour(const BatchArgs a)
     const int gb = xcd_remap(blockIdx.x, a.total_blocks);
     const int l = find_lattice(a, gb);
     const LatDev *__restrict__ L = a.lat[l];
-    const int lb = row_group_remap(slab_remap(gb - a.blk_start[l], L->bpp), a.blk_start[l + 1] - a.blk_start[l]);
+    const int lb = step_block(gb - a.blk_start[l], a.blk_start[l + 1] - a.blk_start[l], L);
+    if (lb < 0) return;   // padding of the lattice's block range
     const int src = a.flags[l] & 1;
     const uint32_t ncell = L->ncell;
     const uint32_t idx = uint32_t(lb) * BLOCK + threadIdx.x;
@@ -1292,11 +1346,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
     if (type == CELL_SOLID) {
         for (int q = 0; q < NQ; ++q) d[q] = hq[q] = R(0);
     } else if (type == CELL_RES) {
-        const R rb = R(L->face_rho[face]), cb = R(L->face_conc[face]);
+        const R rb = R(L->face_rho[face]), cb = R(L->face_conc[face]), drb = R(L->face_rho[face] - 1.0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const R w = weight<R>(q);
-            d[q] = w * (rb - R(1));
+            d[q] = w * drb;
             hq[q] = PHYS == PH_MISCIBLE ? w * eps * cb : (PHYS == PH_IMMISCIBLE ? cb * w * rb : R(0));
         }
         mrho = rb;

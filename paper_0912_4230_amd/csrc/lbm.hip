@@ -432,8 +432,9 @@ lbm_status launch_batch_step(lbm_sim *const *hs, const bool *last, int n)
     memset(&diag, 0, sizeof(diag));
     for (int i = 0; i < n; ++i) {
         const lbm_sim *h = hs[i];
+        // every lattice's range starts on a whole XCD row group (row_group_remap)
         a.blk_start[i] = total;
-        total += h->nblocks;
+        total += (h->nblocks + XCD_GROUP - 1) / XCD_GROUP * XCD_GROUP;
         a.lat[i] = h->dev;
         const long long t = h->steps + 1;
         const bool dg = diag_step(h, t, last[i]);
@@ -638,7 +639,17 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
 lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
 {
     if (!h || !m) return LBM_EINVAL;
+    // Host-side checks before the handle is touched: a rejected call leaves
+    // a handle (ready or not) exactly as it was.
+    if (!m->eps && !(m->eps_uniform > 0.0 && m->eps_uniform <= 1.0)) return LBM_EINVAL;
+    if (!m->kinv)
+        for (int a = 0; a < 3; ++a)
+            if (!(m->kinv_uniform[a] >= 0.0) || !is_fin(m->kinv_uniform[a])) return LBM_EINVAL;
+    if (m->solid && !h->d.solid_mask) return LBM_EINVAL;
     if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    // From here on the device state is rewritten: the handle is ready again
+    // only when the whole set-up has succeeded.
+    h->ready = 0;
     const size_t n = (size_t)h->host.ncell;
     const size_t rb = real_bytes(h->d.storage);
     LatDev &D = h->host;
@@ -647,11 +658,6 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     D.full_tensor = (h->d.full_tensor && m->kinv) ? 1 : 0;
     D.eps_u = m->eps_uniform;
     for (int a = 0; a < 3; ++a) D.kinv_u[a] = m->kinv_uniform[a];
-    if (!m->eps && !(m->eps_uniform > 0.0 && m->eps_uniform <= 1.0)) return LBM_EINVAL;
-    if (!m->kinv)
-        for (int a = 0; a < 3; ++a)
-            if (!(m->kinv_uniform[a] >= 0.0) || !is_fin(m->kinv_uniform[a])) return LBM_EINVAL;
-    if (m->solid && !h->d.solid_mask) return LBM_EINVAL;
     lbm_status st;
     if ((st = dev_err(hipMemcpyAsync(h->dev, &D, sizeof(LatDev), hipMemcpyHostToDevice, h->stream)))) return st;
     static const int zero = 0;
@@ -700,10 +706,7 @@ lbm_status lbm_set_medium(lbm_t h, const lbm_medium *m)
     if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
     h->steps = 0;
     h->cur = 0;
-    if (err) {
-        h->ready = 0;
-        return LBM_EINVAL;
-    }
+    if (err) return LBM_EINVAL;
     h->ready = 1;
     return LBM_OK;
 }
@@ -841,20 +844,22 @@ lbm_status lbm_solute_totals(lbm_t h, double *totals)
     return LBM_OK;
 }
 
-lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lost)
+lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lambda, double *lost)
 {
     if (!h || h->d.physics != LBM_FREESURF) return LBM_EINVAL;
     if (!h->ready) return LBM_ESTATE;
     if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
     const LatDev *L = h->dev;
-    if (cls || mass) {
+    if (cls || mass || lambda) {
+        const dim3 g(h->nblocks), b(BLOCK);
+        const int c = h->cur;
         switch (h->d.storage) {
-        case LBM_F64: hipLaunchKernelGGL(k_fs_export<double>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
-        case LBM_F32: hipLaunchKernelGGL(k_fs_export<float>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
-        case LBM_BF16_DEV: hipLaunchKernelGGL(k_fs_export<bf16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
-        case LBM_F16_DEV: hipLaunchKernelGGL(k_fs_export<f16_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
-        case LBM_BF16_SPLIT: hipLaunchKernelGGL(k_fs_export<bf16s_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
-        default: hipLaunchKernelGGL(k_fs_export<f16s_t>, dim3(h->nblocks), dim3(BLOCK), 0, h->stream, L, h->cur, cls, mass); break;
+        case LBM_F64: hipLaunchKernelGGL(k_fs_export<double>, g, b, 0, h->stream, L, c, cls, mass, lambda); break;
+        case LBM_F32: hipLaunchKernelGGL(k_fs_export<float>, g, b, 0, h->stream, L, c, cls, mass, lambda); break;
+        case LBM_BF16_DEV: hipLaunchKernelGGL(k_fs_export<bf16_t>, g, b, 0, h->stream, L, c, cls, mass, lambda); break;
+        case LBM_F16_DEV: hipLaunchKernelGGL(k_fs_export<f16_t>, g, b, 0, h->stream, L, c, cls, mass, lambda); break;
+        case LBM_BF16_SPLIT: hipLaunchKernelGGL(k_fs_export<bf16s_t>, g, b, 0, h->stream, L, c, cls, mass, lambda); break;
+        default: hipLaunchKernelGGL(k_fs_export<f16s_t>, g, b, 0, h->stream, L, c, cls, mass, lambda); break;
         }
     }
     lbm_status st;

@@ -159,15 +159,17 @@ class Simulation:
         """Miscible: Sum eps C_k over fluid cells for every solute (FP64 list)."""
         return B.lbm_solute_totals(self.h, self.problem.nspecies)
 
-    def free_surface(self):
+    def free_surface(self, fill: bool = False):
         """Free surface: (classes uint8 (nz,ny,nx) 0 gas / 1 interface / 2 liquid /
-        3 solid, liquid mass float64 (nz,ny,nx), lost excess mass) on the device."""
+        3 solid, liquid mass float64 (nz,ny,nx), lost excess mass) on the device;
+        with fill=True also the fill fractions (float64) before the lost mass."""
         import torch
         nx, ny, nz = self.shape
         cls = torch.empty((nz, ny, nx), dtype=torch.uint8, device=self.device)
         mass = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device)
-        lost = B.lbm_free_surface(self.h, cls.data_ptr(), mass.data_ptr())
-        return cls, mass, lost
+        lam = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device) if fill else None
+        lost = B.lbm_free_surface(self.h, cls.data_ptr(), mass.data_ptr(), lam.data_ptr() if fill else 0)
+        return (cls, mass, lam, lost) if fill else (cls, mass, lost)
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -246,7 +246,7 @@ def test_all_gas_and_rejections():
     assert B.lbm_workspace_bytes(make_desc(q, B.LBM_F32)) == 0
     s2 = Simulation(I.miscible(shape=(8, 8, 8), seed=0), storage="f32")
     lost = C.c_double(0.0)
-    assert B.lib().lbm_free_surface(s2.h, None, None, C.byref(lost)) == B.LBM_EINVAL
+    assert B.lib().lbm_free_surface(s2.h, None, None, None, C.byref(lost)) == B.LBM_EINVAL
     s2.close()
 
 

@@ -129,9 +129,14 @@ def test_precision_form_crop_vs_oracle(storage, crop_oracle):
         report(f"precision crop 64^3 x2000 {st}", out[st])
         sim.close()
     e = out[storage]
-    # measured (MI355X): BF16 rho 3.9e-3, drho 0.40, V' 0.83, C 0.18;
-    # FP16 rho 3.3e-4, drho 0.035, V' 0.066, C 4.2e-3; FP32 rho 2.0e-7,
-    # drho 2.0e-5, V' 3.4e-5, C 2.0e-5
+    # measured (MI355X): BF16 rho 3.9e-3, drho 0.40, V' 0.84, C 0.19;
+    # FP16 rho 3.3e-4, drho 0.034, V' 0.066, C 4.2e-3; BF16 split rho 1.4e-3,
+    # drho 0.15, V' 0.29, C 9.3e-5; FP16 split rho 4.6e-6, drho 4.7e-4, V' 7.9e-3,
+    # C 1.0e-4; FP32 rho 1.9e-7, drho 2.0e-5, V' 3.5e-5, C 2.9e-7.  The FP32
+    # drho and V' sit at the floor of the method's arithmetic in FP32: the
+    # oracle itself run in float reaches drho 7.5e-6 to 9.2e-6 and V' 1.9e-5 to
+    # 2.2e-5 on this crop (the error lives in the two cells next to the inlet
+    # reservoir, where the density jumps).
     bounds = {"bf16": {"rho": 5e-3, "drho": 0.5, "vel": 1.0, "conc": 0.25},
               "f16": {"rho": 5e-4, "drho": 0.05, "vel": 0.1, "conc": 1e-2},
               "bf16s": {"rho": 3e-3, "drho": 0.3, "vel": 0.5, "conc": 5e-4},
@@ -139,7 +144,67 @@ def test_precision_form_crop_vs_oracle(storage, crop_oracle):
     for k, b in bounds.items():
         assert e[k] < b, (k, e[k])
     f = out["f32"]
-    assert f["rho"] < 1e-6 and f["drho"] < 5e-5 and f["vel"] < 1e-4 and f["conc"] < 5e-5
+    assert f["rho"] < 4e-7 and f["drho"] < 4e-5 and f["vel"] < 7e-5 and f["conc"] < 1e-6
+
+
+@pytest.mark.parametrize("storage,pop_tol,mass_tol", [("f32", 2e-7, 1e-7), ("bf16", 3e-4, 1e-6)])
+def test_free_surface_penetration_256_one_step(storage, pop_tol, mass_tol):
+    """The free-surface bench workload (penetration of the 256^3 porous box,
+    liquid in the upper half) in the bench's launch configuration, past the
+    initial conversion of the interface (100 steps): the GPU state (populations,
+    classes, masses, fill fractions) is loaded into the FP64 oracle, which takes
+    the next step over the whole box (Sec. 3: mass exchange, Eq. equilempty,
+    conversions, excess).  The cell classes must be identical everywhere; the
+    populations of the live cells, the masses and the fill fractions of the
+    interface cells must agree within the bounds (the oracle computes in FP64
+    from the stored, rounded state, so the differences are one step's rounding
+    of the storage format)."""
+    import torch
+    from oracle import oracle as O
+    from paper_0912_4230_amd.sim import Simulation
+    n, n0 = 256, 100
+    p = I.penetration(shape=(n, n, n), seed=0)
+    perm = permutation_to_oracle()
+    inv = np.argsort(perm)
+    sim = Simulation(p, storage=storage, diag_every=100)
+    sim.step(n0)
+    cls0, m0, lam0, _ = (t.cpu().numpy() if hasattr(t, "cpu") else t for t in sim.free_surface(fill=True))
+    f0 = sim.populations(0).cpu().numpy().reshape(19, -1)
+    sim.step(1)
+    cls1, m1, lam1, lost1 = (t.cpu().numpy() if hasattr(t, "cpu") else t for t in sim.free_surface(fill=True))
+    f1 = sim.populations(0).cpu().numpy().reshape(19, -1)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    print(f"[fullsize] penetration 256^3 {storage}: GPU state exported after {n0} and {n0 + 1} steps", flush=True)
+    o = O.Oracle(p)
+    o.set_state(0, f0[inv].astype(np.float64), n0)
+    del f0
+    o.fs_set_state(cls0, m0, lam0)
+    o.step(1)
+    co, mo, lost_o = o.fs_state()
+    lam_o = o.moments()[2]
+    fluid = o.cell_types() == 0
+    fo = o.get_state(0)
+    o.close()
+    co, cls1 = co.reshape(-1), cls1.reshape(-1)
+    fl = fluid.reshape(-1)
+    assert np.array_equal(cls1[fl], co[fl]), int((cls1[fl] != co[fl]).sum())
+    live = fl & (co >= 1)
+    ifc = fl & (co == 1)
+    df = 0.0
+    for q in range(19):   # GPU order; one plane at a time keeps the memory down
+        df = max(df, float(np.abs(f1[q][live] - fo[perm[q]][live]).max()))
+    del fo
+    dm = float(np.abs(m1.reshape(-1)[ifc] - mo.reshape(-1)[ifc]).max())
+    dl = float(np.abs(lam1.reshape(-1)[ifc] - lam_o.reshape(-1)[ifc]).max())
+    born = int(((cls0.reshape(-1) == 0) & (co == 1) & fl).sum())
+    print(f"[fullsize] penetration 256^3 {storage} step {n0 + 1}: classes identical over {int(fl.sum())} cells "
+          f"({int(ifc.sum())} interface, {born} new), max|df| {df:.2e} (live cells), max|dm| {dm:.2e}, "
+          f"max|dlambda| {dl:.2e}, lost {lost1:.1e} / {lost_o:.1e}", flush=True)
+    assert ifc.sum() > 10000
+    assert df < pop_tol and dm < mass_tol and dl < mass_tol
+    assert lost1 == 0.0 and lost_o == 0.0
 
 
 def test_free_surface_penetration_256_properties():

@@ -52,7 +52,7 @@ def test_miscible_obstacles_ragged(storage, tol):
     e = errors(g, r, mask)
     report(f"miscible+obstacles 37x29x23 x120 {storage}", e)
     assert e["rho"] < tol and e["conc"] < tol
-    assert e["vel"] < (tol if storage == "f64" else 2e-3)
+    assert e["vel"] < (tol if storage == "f64" else 3e-5)   # measured FP32: 1.02e-5
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
@@ -69,7 +69,7 @@ def test_miscible_obstacles_longitudinal(storage, tol):
     g, r, mask, dg, od = run_pair(p, 150, storage)
     e = errors(g, r, mask)
     report(f"miscible+obstacles longitudinal 20x40x18 x150 {storage}", e)
-    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < 10 * tol
+    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < tol   # measured FP32 V': 3.2e-7
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
@@ -85,7 +85,7 @@ def test_two_fluid_obstacles(storage, tol):
     g, r, mask, dg, od = run_pair(p, 120, storage, chunks=[40, 80])
     e = errors(g, r, mask)
     report(f"two-fluid+obstacles 33x31x29 x120 {storage}", e)
-    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < (tol if storage == "f64" else 1e-4)
+    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < tol   # measured FP32 V': 2.7e-6
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
@@ -100,7 +100,8 @@ def test_obstacles_split_storage():
     g, r, mask, dg, od = run_pair(p, 120, "f16s")
     e = errors(g, r, mask)
     report("miscible+obstacles 37x29x23 x120 f16s", e)
-    assert e["rho"] < 1e-5 and e["conc"] < 3e-4 and np.isfinite(e["vel"])
+    # measured: rho 3.5e-7, drho 9.3e-5, V' 3.0e-4, C 3.8e-6
+    assert e["rho"] < 7e-7 and e["drho"] < 1.9e-4 and e["vel"] < 6e-4 and e["conc"] < 8e-6
 
 
 def test_all_solid_and_single_fluid_cell():

@@ -1,11 +1,13 @@
 """GPU (HIP, through the C ABI) against the FP64 CPU oracle, field by field
 over fluid cells, relative L2.
 
-Tolerances: FP64 kernels 1e-10; FP32 1e-5 for rho and C.  V' in FP32 is
-stated per case: the Darcy velocities of the porous workloads (1e-8..1e-5)
-sit far below the populations, so FP32 round-off of the streamed deviations
-(~1e-8 absolute per step) bounds their relative accuracy; the FP32 bound on
-V' is written per case below.  BF16 / FP16 storage: stated per field.
+Tolerances: FP64 kernels 1e-10; FP32 1e-5 for rho, C and V' (measured on
+MI355X with the sources as they are: V' 3e-7 to 8e-6 in these cases).  The
+Darcy velocities of the porous workloads (1e-8..1e-5) sit far below the
+populations, so the FP32 round-off of the streamed deviations bounds their
+relative accuracy over long runs (the 64^3 crop after 2000 steps: V' 3.5e-5,
+against 1.9e-5 for the oracle's own arithmetic run in FP32).  BF16 / FP16
+storage: stated per field, bounds at about twice the measured errors.
 """
 import numpy as np
 import pytest
@@ -53,7 +55,7 @@ def test_miscible_ragged(storage, tol):
     e = errors(g, r, mask)
     report(f"miscible 37x29x23 x120 {storage}", e)
     assert e["rho"] < tol and e["conc"] < tol
-    assert e["vel"] < (tol if storage == "f64" else 2e-3)
+    assert e["vel"] < tol                       # measured FP32: 8.1e-6
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
@@ -67,7 +69,7 @@ def test_miscible_longitudinal_flow(storage, tol):
     g, r, mask, dg, od = run_pair(p, 150, storage)
     e = errors(g, r, mask)
     report(f"miscible longitudinal 20x40x18 x150 {storage}", e)
-    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < 10 * tol
+    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < tol   # measured FP32 V': 2.8e-7
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
@@ -77,7 +79,7 @@ def test_two_fluid_drop_ragged(storage, tol):
     g, r, mask, dg, od = run_pair(p, 150, storage, chunks=[50, 100])
     e = errors(g, r, mask)
     report(f"two-fluid drop 33x31x29 x150 {storage}", e)
-    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < (tol if storage == "f64" else 1e-4)
+    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < tol   # measured FP32 V': 6.8e-6
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
@@ -93,10 +95,15 @@ def test_reduced_precision_storage_errors(storage):
     g, r, mask, dg, od = run_pair(p, 120, storage)
     e = errors(g, r, mask)
     report(f"miscible 37x29x23 x120 {storage}", e)
-    bounds = {"bf16": {"rho": 1e-3, "conc": 2e-2}, "f16": {"rho": 2e-4, "conc": 5e-3},
-              "bf16s": {"rho": 1e-4, "conc": 2e-3}, "f16s": {"rho": 1e-5, "conc": 3e-4}}[storage]
-    assert e["rho"] < bounds["rho"] and e["conc"] < bounds["conc"]
-    assert np.isfinite(e["vel"])
+    # measured (rho, drho, V', C): BF16 1.3e-5, 3.5e-3, 5.3e-3, 1.1e-3; FP16 2.2e-6,
+    # 5.9e-4, 7.8e-4, 1.8e-4; BF16 split 5.6e-7, 1.5e-4, 2.7e-4, 3.8e-5; FP16 split
+    # 3.2e-7, 8.7e-5, 2.6e-4, 4.8e-6
+    bounds = {"bf16": {"rho": 3e-5, "drho": 7e-3, "vel": 1.1e-2, "conc": 2.2e-3},
+              "f16": {"rho": 5e-6, "drho": 1.2e-3, "vel": 1.6e-3, "conc": 3.6e-4},
+              "bf16s": {"rho": 1.2e-6, "drho": 3e-4, "vel": 5.5e-4, "conc": 8e-5},
+              "f16s": {"rho": 7e-7, "drho": 1.8e-4, "vel": 5.2e-4, "conc": 1e-5}}[storage]
+    for k, b in bounds.items():
+        assert e[k] < b, (k, e[k], b)
 
 
 def test_edge_shapes():
@@ -164,11 +171,13 @@ def test_conservation_periodic_gpu():
     """Exact conservation on the GPU under periodic faces: Sum rho and
     Sum eps C from the FP64 diagnostics, every storage mode."""
     from paper_0912_4230_amd.sim import Simulation
-    # (mass, solute) bounds over 300 steps.  FP64 is exact to round-off; the
-    # hydrodynamic lattice is stored as deviations, so its FP32 drift is far
-    # below the solute's, which is stored as is (measured FP32: 8e-12, 7e-6).
-    tols = {"f64": (1e-13, 1e-12), "f32": (1e-9, 3e-5), "bf16": (1e-2, 5e-2), "f16": (1e-3, 1e-2),
-            "bf16s": (1e-5, 1e-4), "f16s": (1e-5, 1e-4)}
+    # (mass, solute) bounds over 300 steps, about twice the measured drift.
+    # FP64 is exact to round-off.  Measured: FP32 7.8e-12 / 7.7e-8 (with the
+    # FP32 weights summing exactly to 1; the rounded 1/3, 1/18, 1/36 made the
+    # solute grow 9e-6 here), BF16 1.8e-10 / 8.5e-5, FP16 2.0e-9 / 4.0e-5,
+    # BF16 split 1.3e-10 / 2.5e-6, FP16 split 1.8e-8 / 1.3e-6.
+    tols = {"f64": (1e-13, 1e-12), "f32": (2e-11, 2e-7), "bf16": (5e-10, 2e-4), "f16": (5e-9, 1e-4),
+            "bf16s": (3e-10, 6e-6), "f16s": (4e-8, 3e-6)}
     for storage, (tm, ts) in tols.items():
         p = I.miscible(shape=(24, 20, 16), seed=2, reservoirs=False)
         p.G = (1e-5, 2e-6, 0.0)

@@ -58,7 +58,7 @@ def test_three_solutes_against_oracle(storage, tol):
         e[f"C{k}"] = rel_l2(g[2][k], o.species_conc(k), mask)
     report(f"three solutes 37x29x23 x120 {storage}", e)
     assert e["rho"] < tol and all(e[f"C{k}"] < tol for k in range(3))
-    assert e["vel"] < (tol if storage == "f64" else 1e-3)
+    assert e["vel"] < tol   # measured FP32: 8.1e-6
     ot = o.species_totals()
     assert np.abs(np.array(totals) - ot).max() <= (1e-12 if storage == "f64" else 1e-5) * ot.max()
     assert abs(dg[4] - ot[0]) <= (1e-12 if storage == "f64" else 1e-5) * ot[0]

@@ -72,7 +72,7 @@ def test_inclined_rings_miscible_ragged(storage, tol):
     e = errors(g, r, mask)
     report(f"inclined rings 37x29x23 x120 {storage}", e)
     assert e["rho"] < tol and e["conc"] < tol
-    assert e["vel"] < (tol if storage == "f64" else 1e-3)
+    assert e["vel"] < tol   # measured FP32: 9.6e-7 (inclined rings), 3.1e-7 (wood)
     assert abs(dg[4] - od[4]) < 10 * tol * od[4]
 
 
@@ -87,7 +87,7 @@ def test_paper_wood_medium_ragged(storage, tol):
     e = errors(g, r, mask)
     report(f"paper wood medium 37x29x23 x120 {storage}", e)
     assert e["rho"] < tol and e["conc"] < tol
-    assert e["vel"] < (tol if storage == "f64" else 1e-3)
+    assert e["vel"] < tol   # measured FP32: 9.6e-7 (inclined rings), 3.1e-7 (wood)
 
 
 def test_inclined_rings_two_fluid_with_obstacles():
@@ -111,7 +111,8 @@ def test_inclined_rings_split_storage():
     g, r, mask, dg, od = run_pair(p, 120, "f16s")
     e = errors(g, r, mask)
     report("inclined rings 37x29x23 x120 f16s", e)
-    assert e["rho"] < 1e-5 and e["conc"] < 3e-4 and np.isfinite(e["vel"])
+    # measured: rho 3.2e-7, drho 1.5e-5, V' 6.3e-5, C 4.3e-6
+    assert e["rho"] < 7e-7 and e["drho"] < 3e-5 and e["vel"] < 1.3e-4 and e["conc"] < 9e-6
 
 
 def test_non_psd_tensor_rejected():

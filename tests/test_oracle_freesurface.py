@@ -262,3 +262,30 @@ def test_free_surface_laplace_law(orc):
     assert (vals.max() - vals.min()) / vals.mean() < 0.03, vals
     v3 = jump_times_radius(9.0, 0.003)
     assert abs(v3 / vals[1] / 3.0 - 1.0) < 0.08, (v3, vals)
+
+
+def test_state_transfer_continues_bitwise(orc):
+    """A free-surface state taken out of one oracle run (populations, classes,
+    masses, fill fractions) and loaded into a fresh one continues bit for bit
+    like the original run: what the GPU parity tests load is the whole state
+    of a step."""
+    p = I.falling_drop(shape=(40, 36, 1), radius=7.0, G=2e-4)
+    a = orc.Oracle(p)
+    a.step(150)
+    cls, m, lost = a.fs_state()
+    lam = a.moments()[2]
+    f = a.get_state(0)
+    b = orc.Oracle(p)
+    b.set_state(0, f, 150)
+    b.fs_set_state(cls, m, lam)
+    a.step(25)
+    b.step(25)
+    ca, ma, _ = a.fs_state()
+    cb, mb, _ = b.fs_state()
+    assert np.array_equal(ca, cb) and np.array_equal(ma, mb)
+    assert np.array_equal(a.get_state(0), b.get_state(0))
+    ra, rb = a.moments(), b.moments()
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
+    # the drop is interfacial: the transfer carried interface cells
+    assert (cls == 1).sum() > 20

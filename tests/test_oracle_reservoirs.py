@@ -1,0 +1,104 @@
+"""Pins of the oracle's reservoir planes (the pressure inlet / outlet of Sec. 4,
+read as planes of cells held at a fixed equilibrium) through exact steady
+states of the second lattice (no GPU).
+
+With the hydrodynamic lattice at rest (equal reservoir densities, no body
+force, uniform medium) the flow is exactly V' = 0 and the second lattice
+only diffuses.  Summed over the directions that share a component c_x, the
+D3Q19 BGK update of Eqs. equild / boltzeqD is a one-dimensional three-speed
+lattice with weights (1/6, 2/3, 1/6), whose steady state between two planes
+of fixed equilibria is exactly linear.  For pull streaming with relaxation
+time tau, the pre-collision sums of the populations moving in +x and -x at
+a fluid cell are (eps / 6)(C -+ tau b) for C = a + b x (the post-collision
+ones (eps / 6)(C -+ (tau - 1) b) stream into the neighbours), so the fluid
+cell next to a reservoir of concentration C_bc satisfies C(1) - tau b = C_bc.
+Fluid cells x = 1 .. nx-2 between reservoirs at x = 0 and nx-1 then carry
+
+    C(x) = C_in + b (x - 1 + tau),   b = (C_out - C_in) / (nx - 3 + 2 tau),
+
+exactly (the diffusive flux -eps D b, D = (tau - 1/2)/3, is the same through
+every plane).  This fixes the solute reservoir state h = w eps C_bc (a state
+without the porosity would hold eps C_bc / eps per unit porosity and move the
+end value to C_in / eps).
+
+The two-fluid reservoir holds g = C_bc f = C_bc w rho_bc.  With beta = 0 and
+A = 0 the recoloured populations are g~ = C f~ with f at rest, i.e. fully
+relaxed (tau = 1) to C w rho: the same lattice with tau = 1, so the colour
+C = rho_1 / rho is exactly C_in + (C_out - C_in) x / (nx - 1) at any uniform
+density rho = rho_bc (a state without rho_bc would put C_in / rho_bc at the
+inlet).
+"""
+import numpy as np
+
+from paper_0912_4230_amd import inputs as I
+
+
+def linear_profile(nx, c_in, c_out, tau):
+    x = np.arange(1, nx - 1, dtype=np.float64)
+    b = (c_out - c_in) / (nx - 3 + 2.0 * tau)
+    return c_in + b * (x - 1 + tau)
+
+
+def _steps(nx, tau):
+    # slowest diffusive mode ~ exp(-D (pi / L)^2 t); converge it below 1e-15
+    D = (tau - 0.5) / 3.0
+    L = nx - 3 + 2.0 * tau
+    return int(40.0 / (D * (np.pi / L) ** 2))
+
+
+def test_solute_reservoirs_exact_linear_profile(orc):
+    """Miscible mode, eps = 0.5, equal reservoir densities: the steady
+    concentration of the first solute and of a second solute (its own tau_d
+    and reservoir concentrations) is the exact linear profile above."""
+    nx, ny, nz = 14, 3, 2
+    tau1, tau2 = 0.8, 1.2
+    faces = [I.Face() for _ in range(6)]
+    faces[0] = I.Face(kind=I.RESERVOIR, rho=1.0, conc=0.8, conc_x=(0.3,))
+    faces[1] = I.Face(kind=I.RESERVOIR, rho=1.0, conc=0.1, conc_x=(0.7,))
+    p = I.Problem(shape=(nx, ny, nz), physics=I.MISCIBLE, forchheimer=True, tau_d=tau1, faces=faces,
+                  species_tau_d=(tau2,))
+    I.hardening_law(p)
+    p.fill_defaults()
+    p.eps[:] = 0.5
+    p.kinv[:] = 10.0
+    p.c0[0][:] = 0.35
+    p.c0[1][:] = 0.9
+    o = orc.Oracle(p)
+    o.step(max(_steps(nx, tau1), _steps(nx, tau2)))
+    r, v, c = o.moments()
+    assert np.abs(v).max() < 1e-17 and np.abs(r - 1.0).max() < 1e-15
+    for k, (c_in, c_out, tau) in enumerate(((0.8, 0.1, tau1), (0.3, 0.7, tau2))):
+        ck = o.species_conc(k)
+        ex = linear_profile(nx, c_in, c_out, tau)
+        got = ck[:, :, 1:-1]
+        assert np.abs(got - ex[None, None, :]).max() < 1e-12, (k, got[0, 0], ex)
+        # the reservoir planes report their fixed concentration
+        assert np.all(ck[:, :, 0] == c_in) and np.all(ck[:, :, -1] == c_out)
+    o.close()
+
+
+def test_two_fluid_reservoirs_exact_linear_colour(orc):
+    """Two-fluid mode at the uniform density 1.05 of both reservoirs, beta = 0,
+    A = 0: the steady colour is the exact linear profile with tau = 1."""
+    nx, ny, nz = 15, 2, 3
+    rb = 1.05
+    faces = [I.Face() for _ in range(6)]
+    faces[0] = I.Face(kind=I.RESERVOIR, rho=rb, conc=0.9)
+    faces[1] = I.Face(kind=I.RESERVOIR, rho=rb, conc=0.2)
+    p = I.Problem(shape=(nx, ny, nz), physics=I.IMMISCIBLE, tau1=0.7, tau2=1.0, A=0.0, beta=0.0,
+                  faces=faces).fill_defaults()
+    p.rho0[:] = rb
+    p.c0[:] = 0.5
+    o = orc.Oracle(p)
+    o.step(_steps(nx, 1.0))
+    r, v, c = o.moments()
+    assert np.abs(v).max() < 1e-16 and np.abs(r - rb).max() < 1e-14
+    x = np.arange(1, nx - 1, dtype=np.float64)
+    ex = 0.9 + (0.2 - 0.9) * x / (nx - 1)
+    assert np.abs(c[:, :, 1:-1] - ex[None, None, :]).max() < 1e-12, (c[0, 0], ex)
+    assert np.all(c[:, :, 0] == 0.9) and np.all(c[:, :, -1] == 0.2)
+    # steady: Sum rho_1 over the fluid cells no longer changes
+    d0 = o.diag()[4]
+    o.step(50)
+    assert abs(o.diag()[4] / d0 - 1.0) < 1e-13
+    o.close()
