@@ -229,6 +229,20 @@ size_t lbm_workspace_bytes(const lbm_desc *d);
 lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes,
                       void *hip_stream, lbm_t *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_create
+ * without a workspace argument.  The lattice lives in a static workspace
+ * that the library holds on every GPU it runs on (64 MiB per device, in its
+ * code object, kept until the process ends), so neither this call nor any
+ * later call on the handle allocates anything, on the device or the host.
+ * One such lattice per device at a time: LBM_ESTATE while another handle of
+ * this call on the current device is alive (lbm_destroy releases it);
+ * LBM_ENOMEM if the lattice needs more than 64 MiB (lbm_workspace_bytes);
+ * LBM_EINVAL for an invalid description.  Results are bitwise those of
+ * lbm_create with a caller workspace.  Every other call takes the handle as
+ * usual (lbm_step_batch may mix it with lattices in caller workspaces). */
+lbm_status lbm_create_static(const lbm_desc *d, void *hip_stream, lbm_t *out);
+
 /* Copy the medium and the initial fields in and set the populations to their
  * equilibria (Eqs. equilc1/2, equild; two-fluid: g = C f).  Validates the
  * fields of every non-solid cell on the device (eps in (0,1], K^-1 >= 0,

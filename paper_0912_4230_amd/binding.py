@@ -20,7 +20,7 @@ LBM_MAX_SPECIES = 4
 
 STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV,
                  "bf16s": LBM_BF16_SPLIT, "f16s": LBM_F16_SPLIT}
-EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_set_medium", "lbm_step", "lbm_step_batch",
+EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_create_static", "lbm_set_medium", "lbm_step", "lbm_step_batch",
             "lbm_moments", "lbm_populations", "lbm_solute_totals", "lbm_free_surface", "lbm_steps_done", "lbm_destroy",
             "lbm_lattice", "lbm_strerror"]
 
@@ -78,6 +78,8 @@ def lib():
         L.lbm_workspace_bytes.argtypes = [C.POINTER(lbm_desc)]
         L.lbm_create.restype = C.c_int
         L.lbm_create.argtypes = [C.POINTER(lbm_desc), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_create_static.restype = C.c_int
+        L.lbm_create_static.argtypes = [C.POINTER(lbm_desc), vp, C.POINTER(vp)]
         L.lbm_set_medium.restype = C.c_int
         L.lbm_set_medium.argtypes = [vp, C.POINTER(lbm_medium)]
         L.lbm_step.restype = C.c_int
@@ -119,6 +121,14 @@ def lbm_create(desc: lbm_desc, workspace_ptr: int, ws_bytes: int, stream_ptr: in
     h = C.c_void_p()
     _check(lib().lbm_create(C.byref(desc), C.c_void_p(workspace_ptr), C.c_size_t(ws_bytes),
                             C.c_void_p(stream_ptr), C.byref(h)), "lbm_create")
+    return h
+
+
+def lbm_create_static(desc: lbm_desc, stream_ptr: int = 0):
+    """Handle of a lattice in the library's static workspace of the current
+    device (no allocation); raises LbmError on failure."""
+    h = C.c_void_p()
+    _check(lib().lbm_create_static(C.byref(desc), C.c_void_p(stream_ptr), C.byref(h)), "lbm_create_static")
     return h
 
 

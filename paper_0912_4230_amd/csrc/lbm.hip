@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "kernels.hpp"
@@ -229,6 +230,7 @@ struct lbm_sim {
     int ready;          // medium set
     int nblocks;
     int device;
+    int in_scratch;     // workspace = this device's scratch array (lbm_create_static)
 };
 
 namespace {
@@ -516,28 +518,24 @@ size_t lbm_workspace_bytes(const lbm_desc *d)
     return layout(d).total;
 }
 
-lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_t *out)
+}  // extern "C"
+
+namespace {
+
+// Fill the zeroed handle h for description d (valid) with its workspace at
+// dev_workspace (ws_bytes >= the layout's total) on device `device`.  No GPU
+// call.
+void setup_handle(lbm_sim *h, const lbm_desc *d, void *dev_workspace, size_t ws_bytes, void *hip_stream, int device)
 {
-    if (!out) return LBM_EINVAL;
-    *out = nullptr;
-    if (!valid_desc(d) || !dev_workspace) return LBM_EINVAL;
-    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN) return LBM_EINVAL;
     const Layout L = layout(d);
-    if (ws_bytes < L.total) return LBM_ENOMEM;
-    lbm_sim *h = new (std::nothrow) lbm_sim;
-    if (!h) return LBM_ENOMEM;
-    memset(h, 0, sizeof(*h));
     h->d = *d;
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->ws = static_cast<char *>(dev_workspace);
     h->ws_bytes = ws_bytes;
     h->lay = L;
+    h->device = device;
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     h->nblocks = int((n + BLOCK - 1) / BLOCK);
-    if (hipGetDevice(&h->device) != hipSuccess) {
-        delete h;
-        return LBM_EDEVICE;
-    }
 
     LatDev &D = h->host;
     D.nx = d->nx;
@@ -632,6 +630,71 @@ lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, v
     D.diag = reinterpret_cast<double *>(w + L.diag);
     D.err = reinterpret_cast<int *>(w + L.err);
     h->dev = reinterpret_cast<LatDev *>(w + L.lat);
+}
+
+// ---------------------------------------------------------------------------
+// Lattices for callers that cannot allocate (lbm_create_static): the
+// workspace is this file-scope array, one copy per GPU, placed on every
+// device the library runs on when the code object is loaded and held until
+// the process ends.  In host code `scratch` names a host-side stand-in: its
+// device address on each device comes from hipGetSymbolAddress (taken once
+// per device, with that device current) and only that address is used.
+// One lattice at a time holds a device's array (with its handle in a static
+// slot); the set-up of lbm_set_medium writes every byte of the layout that a
+// step reads, so the contents left by an earlier lattice do not matter.
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+constexpr int MAX_DEVICES = 64;
+
+__device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];        // device address of scratch per device, once looked up
+lbm_sim scratch_sim[MAX_DEVICES];      // the handle of the lattice holding it
+bool scratch_held[MAX_DEVICES];
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_create(const lbm_desc *d, void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_t *out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (!valid_desc(d) || !dev_workspace) return LBM_EINVAL;
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN) return LBM_EINVAL;
+    if (ws_bytes < layout(d).total) return LBM_ENOMEM;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return LBM_EDEVICE;
+    lbm_sim *h = new (std::nothrow) lbm_sim;
+    if (!h) return LBM_ENOMEM;
+    memset(h, 0, sizeof(*h));
+    setup_handle(h, d, dev_workspace, ws_bytes, hip_stream, device);
+    *out = h;
+    return LBM_OK;
+}
+
+lbm_status lbm_create_static(const lbm_desc *d, void *hip_stream, lbm_t *out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (!valid_desc(d)) return LBM_EINVAL;
+    if (layout(d).total > SCRATCH_BYTES) return LBM_ENOMEM;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return LBM_EDEVICE;
+    if (device < 0 || device >= MAX_DEVICES) return LBM_EDEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_held[device]) return LBM_ESTATE;
+    if (!scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBM_EDEVICE;
+        if (reinterpret_cast<uintptr_t>(p) % ALIGN) return LBM_EDEVICE;
+        scratch_ptr[device] = p;
+    }
+    lbm_sim *h = &scratch_sim[device];
+    memset(h, 0, sizeof(*h));
+    setup_handle(h, d, scratch_ptr[device], SCRATCH_BYTES, hip_stream, device);
+    h->in_scratch = 1;
+    scratch_held[device] = true;
     *out = h;
     return LBM_OK;
 }
@@ -876,6 +939,13 @@ long long lbm_steps_done(lbm_t h) { return h ? h->steps : -1; }
 lbm_status lbm_destroy(lbm_t h)
 {
     if (!h) return LBM_EINVAL;
+    if (h->in_scratch) {
+        // the array stays on the device; only the hold is released
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        scratch_held[h->device] = false;
+        h->in_scratch = 0;
+        return LBM_OK;
+    }
     delete h;
     return LBM_OK;
 }

@@ -59,7 +59,7 @@ class Simulation:
     """
 
     def __init__(self, problem: I.Problem, storage=B.LBM_F32, device="cuda:0", stream=None,
-                 diag_every: int = 0, uniform_medium: bool = True):
+                 diag_every: int = 0, uniform_medium: bool = True, static_workspace: bool = False):
         import torch
         if isinstance(storage, str):
             storage = B.STORAGE_NAMES[storage]
@@ -74,8 +74,14 @@ class Simulation:
             raise B.LbmError(B.LBM_EINVAL, "lbm_workspace_bytes")
         self.nbytes = nbytes
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.h = B.lbm_create(self.desc, self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
+        if static_workspace:
+            # the library's own static workspace of this device (lbm_create_static)
+            self.ws = None
+            with torch.cuda.device(self.device):
+                self.h = B.lbm_create_static(self.desc, self.stream.cuda_stream)
+        else:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.h = B.lbm_create(self.desc, self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
         self.shape = tuple(p.shape)
         self._set_medium(p, uniform_medium)
 
