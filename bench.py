@@ -87,7 +87,7 @@ def time_gpu(problem, storage, steps, warmup):
     return ms, dg
 
 
-def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50):
+def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50, single_mlups=None):
     """The serving workload: 64 requests, Poisson arrivals at 4/s, cubic edge
     log-uniform in [48, 192], 70% miscible / 30% two-fluid, 500-5000 steps,
     seeded spruce-like media (anisotropy U[10, 200]), admitted under an HBM
@@ -109,38 +109,19 @@ def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50):
         out[st] = {"p50_s": round(res["p50_s"], 3), "p99_s": round(res["p99_s"], 3),
                    "mean_s": round(res["mean_s"], 3), "aggregate_MLUPS": round(res["aggregate_mlups"], 1),
                    "completed": res["completed"], "failed": res["failed"], "max_active": res["max_active"],
-                   "span_s": round(res["span_s"], 2)}
+                   "span_s": round(res["span_s"], 2), "ticks": res["ticks"],
+                   "gpu_busy_s": round(res["busy_s"], 2), "gpu_busy_fraction": round(res["busy_fraction"], 3)}
+        if single_mlups and st in single_mlups:
+            out[st]["aggregate_vs_single_lattice_256"] = round(res["aggregate_mlups"] / single_mlups[st], 3)
         log(f"bench: serving {st}: {out[st]}")
     return out
 
 
 def medium_parallel(n, seed=0, slabs=16):
     """The n^3 miscible problem with its medium generated in z-slabs in
-    parallel (the counter-based generator makes every slab equal to the
-    corresponding crop of the full medium)."""
-    import numpy as np
-    from concurrent.futures import ThreadPoolExecutor
+    parallel (inputs.miscible_parallel)."""
     from paper_0912_4230_amd import inputs as I
-    p = I.miscible(shape=(n, n, 2), seed=seed)
-    p.shape = (n, n, n)
-    dz = (n + slabs - 1) // slabs
-    parts = [(z0, min(dz, n - z0)) for z0 in range(0, n, dz)]
-    eps = np.empty((n, n, n), dtype=np.float32)
-    kinv = np.empty((3, n, n, n), dtype=np.float32)
-
-    def gen(part):
-        z0, nzp = part
-        e, k = I.spruce_medium((n, n, nzp), seed=seed, ratio=100.0, origin=(0, 0, z0))
-        eps[z0:z0 + nzp] = e
-        kinv[:, z0:z0 + nzp] = k
-
-    with ThreadPoolExecutor(8) as pool:
-        list(pool.map(gen, parts))
-    p.eps, p.kinv = eps, kinv
-    p.rho0 = np.ones((n, n, n), dtype=np.float32)
-    p.vel0 = np.zeros((3, n, n, n), dtype=np.float32)
-    p.c0 = np.zeros((n, n, n), dtype=np.float32)
-    return p
+    return I.miscible_parallel(n, seed=seed, slabs=slabs)
 
 
 def precision_leg(n=512, steps=2000, timed=200, compare=True):
@@ -529,7 +510,10 @@ def main():
     if not args.no_freesurface and args.storage == "f32":
         out["free_surface"] = freesurface_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_serve:
-        out["serving"] = serving_leg()
+        single = {"f32": mlups} if args.storage == "f32" else {}
+        if "reduced_storage" in out:
+            single["bf16"] = out["reduced_storage"]["bf16"]["MLUPS"]
+        out["serving"] = serving_leg(single_mlups=single)
     if args.precision:
         out["precision_form"] = precision_leg()
     elif not args.no_512 and args.storage == "f32":

@@ -302,6 +302,15 @@ lbm_status lbm_solute_totals(lbm_t h, double *totals);
  * Synchronises the stream. */
 lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *lambda, double *lost);
 
+/* Issue the handle's later calls on hip_stream (a hipStream_t, NULL: the
+ * default stream) instead of the stream given to lbm_create.  No GPU call:
+ * the library does not order the new stream after work already issued on
+ * the old one, the caller does (an event, or a synchronisation).  Serving
+ * uses it to set lattices up and read them back on a second stream while the
+ * batched steps of the others run on the first (lbm_step_batch takes handles
+ * of one stream).  LBM_EINVAL for a NULL handle. */
+lbm_status lbm_set_stream(lbm_t h, void *hip_stream);
+
 /* Completed steps since lbm_set_medium, or -1 for a NULL handle. */
 long long lbm_steps_done(lbm_t h);
 

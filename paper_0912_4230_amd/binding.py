@@ -21,7 +21,7 @@ LBM_MAX_SPECIES = 4
 STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LBM_F16_DEV,
                  "bf16s": LBM_BF16_SPLIT, "f16s": LBM_F16_SPLIT}
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_create_static", "lbm_set_medium", "lbm_step", "lbm_step_batch",
-            "lbm_moments", "lbm_populations", "lbm_solute_totals", "lbm_free_surface", "lbm_steps_done", "lbm_destroy",
+            "lbm_moments", "lbm_populations", "lbm_solute_totals", "lbm_free_surface", "lbm_set_stream", "lbm_steps_done", "lbm_destroy",
             "lbm_lattice", "lbm_strerror"]
 
 
@@ -78,6 +78,8 @@ def lib():
         L.lbm_workspace_bytes.argtypes = [C.POINTER(lbm_desc)]
         L.lbm_create.restype = C.c_int
         L.lbm_create.argtypes = [C.POINTER(lbm_desc), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_set_stream.restype = C.c_int
+        L.lbm_set_stream.argtypes = [vp, vp]
         L.lbm_create_static.restype = C.c_int
         L.lbm_create_static.argtypes = [C.POINTER(lbm_desc), vp, C.POINTER(vp)]
         L.lbm_set_medium.restype = C.c_int
@@ -130,6 +132,10 @@ def lbm_create_static(desc: lbm_desc, stream_ptr: int = 0):
     h = C.c_void_p()
     _check(lib().lbm_create_static(C.byref(desc), C.c_void_p(stream_ptr), C.byref(h)), "lbm_create_static")
     return h
+
+
+def lbm_set_stream(h, stream_ptr: int = 0) -> int:
+    return _check(lib().lbm_set_stream(h, C.c_void_p(stream_ptr or None)), "lbm_set_stream")
 
 
 def lbm_set_medium(h, medium: lbm_medium) -> int:

@@ -1,5 +1,6 @@
 """Build the gfx950 shared library libporolbm.so (in the package directory)
-from csrc/ with hipcc.  Every call compiles from source."""
+from csrc/ with hipcc, and the measurement probe library libporolbm_probe.so
+(profile_run only).  Every call compiles from source."""
 import os
 import subprocess
 import sys
@@ -18,13 +19,17 @@ FLAGS = [
 ]
 
 
+PROBE_LIB = os.path.join(HERE, "libporolbm_probe.so")
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "lbm.hip"), "-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    """Compile the lattice library and the measurement probe library."""
+    for src, out in ((os.path.join(CSRC, "lbm.hip"), LIB), (os.path.join(CSRC, "probe.hip"), PROBE_LIB)):
+        cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", out + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
     return LIB
 
 

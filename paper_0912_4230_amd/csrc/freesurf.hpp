@@ -53,6 +53,11 @@ struct FsDev {
     uint32_t *hlist[2];
     uint32_t *hcount[2];
     uint32_t *hpos[2];
+    // per row of 256 cells, one byte per population copy: nonzero when pass 1
+    // has work in the row (a liquid or interface cell, or a cell flagged in
+    // the last step, whose flag pass 1 clears); written by the last class
+    // pass for the next step, all rows set at set-up
+    unsigned char *rowlive[2];
 };
 
 // List a row for the next pass 1 (buffer buf), once: the first caller claims
@@ -235,6 +240,9 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
         if (row >= nrow) return;
     } else {
         row = uint32_t(c.lb) - cap;
+        // a row without liquid, interface or flagged cells (all gas, solid):
+        // its populations, classes and flags stay as they are (uniform)
+        if (!ldg<uint8_t>(F->rowlive[src], row)) return;
     }
     c.idx = row * BLOCK + threadIdx.x;
     const uint32_t idx = c.idx, ncell = c.ncell;
@@ -611,64 +619,90 @@ __global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
 // of their converting neighbours (FS_RECV cells only); marks of cells that
 // were not interface cells cleared.  The fill fraction of every other
 // interface cell was written by pass 1.
+// the bytes of a 16-byte group of classes that are liquid or interface
+__device__ inline bool any_live(const u32x4 &c)
+{
+    bool r = false;
+#pragma unroll
+    for (int k = 0; k < FS_CPT; ++k) {
+        const int b = byte_of(c, k);
+        r = r || b == FS_IF || b == FS_LIQ;
+    }
+    return r;
+}
+
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
 {
     using R = typename Codec<S>::R;
-    [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsTile t = fs_tile(a);
-    if (t.base >= t.ncell) return;
     const LatDev *__restrict__ L = t.L;
     const FsDev *__restrict__ F = t.F;
     const int dst = (t.flags & 1) ^ 1;
-    const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
-    if (!any_byte(f) && !any_byte(m2)) return;
-    for (int k = 0; k < FS_CPT; ++k) {
-        const uint32_t idx = t.base + k;
-        if (idx >= t.ncell) break;
-        const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
-        if (!w1 && !w2) continue;
-        if (w1 == FS_FILL) {
-            stg<uint8_t>(F->cls, idx, FS_LIQ);
-            continue;
-        }
-        if (empties(w1, w2)) {
-            stg<uint8_t>(F->cls, idx, FS_GAS);
-            continue;
-        }
-        if (!(w2 & (FS_BORN | FS_TO_IF | FS_RECV))) continue;   // kept, no share
-        double m, r;
-        if (w2 & FS_BORN) {
-            m = 0.0;
-            r = ldg<double>(F->rho, idx);
-        } else if (w2 & FS_TO_IF) {     // a liquid cell: m = its density
-            R o[NQ];
-            load_cell<S>(L->f[dst], L->fm[dst], L->pstride, idx, o);
-            R dr = 0;
+    // do this thread's cells keep their row in the next pass 1: a cell that is
+    // liquid or interface after this step (it was, or was born), or one
+    // flagged in this step (pass 1 clears its flag)
+    bool keep = false;
+    if (t.base < t.ncell) {
+        const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base), c0 = ld16(F->cls, t.base);
+        keep = any_byte(f) || any_live(c0) || ((m2.x | m2.y | m2.z | m2.w) & 0x01010101u * FS_BORN) != 0u;
+        if (any_byte(f) || any_byte(m2)) {
+            for (int k = 0; k < FS_CPT; ++k) {
+                const uint32_t idx = t.base + k;
+                if (idx >= t.ncell) break;
+                const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
+                if (!w1 && !w2) continue;
+                if (w1 == FS_FILL) {
+                    stg<uint8_t>(F->cls, idx, FS_LIQ);
+                    continue;
+                }
+                if (empties(w1, w2)) {
+                    stg<uint8_t>(F->cls, idx, FS_GAS);
+                    continue;
+                }
+                if (!(w2 & (FS_BORN | FS_TO_IF | FS_RECV))) continue;   // kept, no share
+                double m, r;
+                if (w2 & FS_BORN) {
+                    m = 0.0;
+                    r = ldg<double>(F->rho, idx);
+                } else if (w2 & FS_TO_IF) {     // a liquid cell: m = its density
+                    R o[NQ];
+                    load_cell<S>(L->f[dst], L->fm[dst], L->pstride, idx, o);
+                    R dr = 0;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) dr += o[q];
-            r = 1.0 + double(dr);
-            m = r;
-        } else {
-            m = ldg<double>(F->mass, idx);
-            r = ldg<double>(F->rho, idx);
-        }
-        if (w2 & FS_RECV) {
-            const Nbr b = nbr_of(L, idx);
-            for_links([&](auto qc) {
-                constexpr int Q = decltype(qc)::value;
-                const uint32_t j = shifted<Q, 1>(b);
-                if (converts(F, j)) m += ldg<double>(F->share, j);
-            });
-        }
-        stg<double>(F->mass, idx, m);
-        stg<double>(F->lam[dst], idx, m / r);
-        if (w2 & (FS_BORN | FS_TO_IF)) {
-            stg<uint8_t>(F->cls, idx, FS_IF);
-            stg<uint8_t>(F->w2, idx, 0);
-            fs_list_row(F, dst, idx / BLOCK, (t.ncell + BLOCK - 1) / BLOCK);
+                    for (int q = 0; q < NQ; ++q) dr += o[q];
+                    r = 1.0 + double(dr);
+                    m = r;
+                } else {
+                    m = ldg<double>(F->mass, idx);
+                    r = ldg<double>(F->rho, idx);
+                }
+                if (w2 & FS_RECV) {
+                    const Nbr b = nbr_of(L, idx);
+                    for_links([&](auto qc) {
+                        constexpr int Q = decltype(qc)::value;
+                        const uint32_t j = shifted<Q, 1>(b);
+                        if (converts(F, j)) m += ldg<double>(F->share, j);
+                    });
+                }
+                stg<double>(F->mass, idx, m);
+                stg<double>(F->lam[dst], idx, m / r);
+                if (w2 & (FS_BORN | FS_TO_IF)) {
+                    stg<uint8_t>(F->cls, idx, FS_IF);
+                    stg<uint8_t>(F->w2, idx, 0);
+                    fs_list_row(F, dst, idx / BLOCK, (t.ncell + BLOCK - 1) / BLOCK);
+                }
+            }
         }
     }
+    // one flag per row of BLOCK cells: the BLOCK / FS_CPT consecutive lanes
+    // that cover the row vote, the first of them writes it
+    constexpr int TPR = BLOCK / FS_CPT;
+    static_assert(64 % TPR == 0, "a row's lanes lie in one wave");
+    const uint64_t vote = __builtin_amdgcn_ballot_w64(keep);
+    const int lane = threadIdx.x & 63;
+    if (lane % TPR == 0 && t.base < t.ncell)
+        stg<uint8_t>(F->rowlive[dst], t.base / BLOCK, ((vote >> lane) & ((uint64_t(1) << TPR) - 1)) != 0 ? 1 : 0);
 }
 
 // Moment steps, after pass 5 (one thread per cell, the step grid): rho, V'
@@ -773,10 +807,12 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const 
             part[4] = l * r0;
         }
     }
-    // empty launch-order lists
+    // empty launch-order lists; every row visited by the first pass 1
     if (threadIdx.x == 0) {
         stg<uint32_t>(F->hpos[0], blockIdx.x, 0u);
         stg<uint32_t>(F->hpos[1], blockIdx.x, 0u);
+        stg<uint8_t>(F->rowlive[0], blockIdx.x, 1);
+        stg<uint8_t>(F->rowlive[1], blockIdx.x, 1);
         if (blockIdx.x == 0) {
             stg<uint32_t>(F->hcount[0], 0, 0u);
             stg<uint32_t>(F->hcount[1], 0, 0u);

@@ -46,13 +46,16 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 // the same HBM channels (512^3, two runs each: BF16 5.52 -> 4.38-4.57 ms,
 // FP16 5.49 -> 4.49, FP32 8.29 -> 8.03, split forms unchanged), while at
 // 256^3 (64 MiB planes) the larger pad measured 12% slower in FP32.
+#ifndef PLBM_BIG_PAD
+#define PLBM_BIG_PAD (512 * 1024 + 512)
+#endif
 size_t plane_stride(const lbm_desc *d)
 {
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     const size_t sb = storage_bytes(d->storage), per = 256 / sb;
     const size_t base = (n + per - 1) / per * per, bytes = base * sb;
     const size_t MiB = size_t(1) << 20;
-    const size_t pad = (bytes >= 256 * MiB && bytes % MiB == 0) ? 512 * 1024 + 512 : 512;
+    const size_t pad = (bytes >= 256 * MiB && bytes % MiB == 0) ? size_t(PLBM_BIG_PAD) : 512;
     return base + pad / sb;
 }
 
@@ -163,7 +166,7 @@ Layout layout(const lbm_desc *d)
     // free surface: the FsDev block (+ the lost-mass counter), three byte
     // planes, five double planes (m, two of lambda, rho, share) and the 3
     // double planes of V', and two launch-order sets (row list, per-row
-    // positions, count)
+    // positions, count, per-row live flags)
     L.fs = o;        if (fs) o = align_up(o + sizeof(FsDev) + sizeof(double));
     L.fs_cls = o;    if (fs) o = align_up(o + n);
     L.fs_w1 = o;     if (fs) o = align_up(o + n);
@@ -173,8 +176,8 @@ Layout layout(const lbm_desc *d)
     L.fs_rho = o;    if (fs) o = align_up(o + n * sizeof(double));
     L.fs_share = o;  if (fs) o = align_up(o + n * sizeof(double));
     L.fs_u = o;      if (fs) o = align_up(o + 3 * n * sizeof(double));
-    const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4);
-    L.fs_hot = o;    if (fs) o = align_up(o + 2 * (2 * rows4 + 256));
+    const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4), rows1 = align_up((n + BLOCK - 1) / BLOCK);
+    L.fs_hot = o;    if (fs) o = align_up(o + 2 * (2 * rows4 + 256 + rows1));
     // further solutes: the MsDev block, per solute two population copies and,
     // split storage, two mass planes
     const int nsx = extra_species(d);
@@ -617,12 +620,13 @@ void setup_handle(lbm_sim *h, const lbm_desc *d, void *dev_workspace, size_t ws_
         F.share = reinterpret_cast<double *>(w + L.fs_share);
         F.u = reinterpret_cast<double *>(w + L.fs_u);
         F.lost = reinterpret_cast<double *>(w + L.fs + sizeof(FsDev));
-        const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4);
+        const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4), rows1 = align_up((n + BLOCK - 1) / BLOCK);
         for (int c = 0; c < 2; ++c) {
-            char *base = w + L.fs_hot + c * (2 * rows4 + 256);
+            char *base = w + L.fs_hot + c * (2 * rows4 + 256 + rows1);
             F.hlist[c] = reinterpret_cast<uint32_t *>(base);
             F.hpos[c] = reinterpret_cast<uint32_t *>(base + rows4);
             F.hcount[c] = reinterpret_cast<uint32_t *>(base + 2 * rows4);
+            F.rowlive[c] = reinterpret_cast<unsigned char *>(base + 2 * rows4 + 256);
         }
         D.fs = w + L.fs;
     }
@@ -931,6 +935,13 @@ lbm_status lbm_free_surface(lbm_t h, unsigned char *cls, double *mass, double *l
     if ((st = dev_err(hipMemcpyAsync(&lo, h->fs.lost, sizeof(double), hipMemcpyDeviceToHost, h->stream)))) return st;
     if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
     if (lost) *lost = lo;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_t h, void *hip_stream)
+{
+    if (!h) return LBM_EINVAL;
+    h->stream = static_cast<hipStream_t>(hip_stream);
     return LBM_OK;
 }
 

@@ -23,9 +23,11 @@ CSRC = os.path.join(HERE, "csrc")
 
 
 def source_sha() -> str:
+    """SHA-256 of the lattice library's kernel sources (the probe library's
+    source is not part of it)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hpp", ".hip", ".h", ".cpp")):
+        if name.endswith((".hpp", ".hip", ".h", ".cpp")) and name != "probe.hip":
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())

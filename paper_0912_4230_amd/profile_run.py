@@ -1,13 +1,16 @@
 """Small fixed workloads to run under rocprofv3 (kernel trace or PMC counters).
 
   python -m paper_0912_4230_amd.profile_run step --physics miscible --size 256 --storage f32 --steps 10
-  python -m paper_0912_4230_amd.profile_run copy --mib 2048 --reps 5
+  python -m paper_0912_4230_amd.profile_run copy --mib 2048 --reps 5 [--kernel f4]
 
 `step` sets up one lattice of the chosen workload and runs the given number
 of steps (one step kernel launch each, plus the colour pass in two-fluid
-mode, or the five launches of a free-surface step); `copy` runs torch's device-to-device copy of a buffer of known size,
-the reference kernel used to scale the FETCH_SIZE / WRITE_SIZE counters to
-bytes.  Both print what they ran, with the byte counts of one launch.
+mode, or the five launches of a free-surface step); `copy` runs torch's
+device-to-device copy of a buffer of known size, the reference kernel used
+to scale the FETCH_SIZE / WRITE_SIZE counters to bytes, or (--kernel f4) the
+float4 non-temporal streaming copy of the probe library, the practical
+ceiling of a read-once / write-once stream.  Both print what they ran, with
+the byte counts of one launch.
 """
 import argparse
 import os
@@ -22,7 +25,7 @@ if ROOT not in sys.path:
 def problem(physics: str, n: int):
     from paper_0912_4230_amd import inputs as I
     if physics == "miscible":
-        return I.miscible(shape=(n, n, n), seed=0)
+        return I.miscible_parallel(n, seed=0) if n >= 384 else I.miscible(shape=(n, n, n), seed=0)
     if physics == "immiscible":
         return I.drop(shape=(n, n, n), radius=20.0 * n / 128.0)
     if physics == "single":
@@ -59,15 +62,90 @@ def run_step(args):
 
 
 def run_copy(args):
+    """torch's device copy (the counter calibration reference), or with
+    --kernel f4 the probe library's float4 non-temporal streaming copy; the
+    rate is timed with HIP events on the stream of the launches."""
+    import ctypes
     import torch
     n = args.mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    if args.kernel == "f4":
+        from paper_0912_4230_amd.build_lib import PROBE_LIB
+        if not os.path.exists(PROBE_LIB):
+            raise SystemExit("libporolbm_probe.so is not built: run __graft_entry__.build()")
+        probe = ctypes.CDLL(PROBE_LIB)
+        probe.probe_copy_f4.restype = ctypes.c_int
+        probe.probe_copy_f4.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.c_int]
+
+        def launch():
+            rc = probe.probe_copy_f4(b.data_ptr(), a.data_ptr(), n * 4, stream.cuda_stream, args.blocks)
+            if rc:
+                raise SystemExit(f"probe_copy_f4 failed ({rc})")
+    else:
+        def launch():
+            b.copy_(a)
+    launch()
     torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
     for _ in range(args.reps):
-        b.copy_(a)
+        launch()
+    t1.record(stream)
     torch.cuda.synchronize()
-    print(f"profile_run copy: {args.reps} launches, each reads {n * 4} B and writes {n * 4} B", flush=True)
+    ms = t0.elapsed_time(t1) / args.reps
+    print(f"profile_run copy ({args.kernel}): {args.reps + 1} launches, each reads {n * 4} B and writes {n * 4} B; "
+          f"{ms:.3f} ms per launch, {2 * n * 4 / ms / 1e6:.1f} GB/s (HIP events)", flush=True)
+
+
+def run_streams(args):
+    """The probe library's 38-stream kernel (38 planes read and written, one
+    cell per thread) over n = size^3 cells of 4- or 2-byte elements in the
+    plane-major layout of the lattice workspace (planes `pad` elements apart
+    beyond n) or slice-major (all 38 planes of each z-slice of size^2 cells
+    contiguous); HIP-event rate."""
+    import ctypes
+    import torch
+    from paper_0912_4230_amd.build_lib import PROBE_LIB
+    if not os.path.exists(PROBE_LIB):
+        raise SystemExit("libporolbm_probe.so is not built: run __graft_entry__.build()")
+    probe = ctypes.CDLL(PROBE_LIB)
+    probe.probe_streams38.restype = ctypes.c_int
+    probe.probe_streams38.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_size_t,
+                                      ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
+    n = args.size ** 3
+    if args.layout == "plane":
+        pstride, slice_, sstride = n + args.pad, 0, 0
+        total = 38 * pstride
+    else:
+        pstride, slice_, sstride = 0, args.size ** 2, args.size ** 2 + args.pad
+        total = args.size * 38 * sstride
+    dt = torch.float32 if args.elem == 4 else torch.int16
+    a = torch.zeros(total, dtype=dt, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        rc = probe.probe_streams38(b.data_ptr(), a.data_ptr(), n, pstride, slice_, sstride, stream.cuda_stream,
+                                   args.elem)
+        if rc:
+            raise SystemExit(f"probe_streams38 failed ({rc})")
+    launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.reps):
+        launch()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.reps
+    print(f"profile_run streams: {args.layout}-major, {args.size}^3 cells, 38 planes of {args.elem}-byte elements, "
+          f"pad {args.pad} elements: {ms:.3f} ms per launch, {2 * 38 * args.elem * n / ms / 1e6:.1f} GB/s "
+          f"(HIP events)", flush=True)
 
 
 def main():
@@ -81,11 +159,19 @@ def main():
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=2048)
     c.add_argument("--reps", type=int, default=5)
+    c.add_argument("--kernel", default="torch", choices=["torch", "f4"])
+    c.add_argument("--blocks", type=int, default=8192, help="grid of the f4 probe (256 threads per block)")
+    t = sub.add_parser("streams")
+    t.add_argument("--size", type=int, default=256)
+    t.add_argument("--layout", default="plane", choices=["plane", "slice"])
+    t.add_argument("--pad", type=int, default=128, help="elements of padding after each plane (slice)")
+    t.add_argument("--elem", type=int, default=4, choices=[4, 2], help="element bytes")
+    t.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
     from paper_0912_4230_amd import binding
     if not os.path.exists(binding.LIB_PATH):
         raise SystemExit("libporolbm.so is not built: run __graft_entry__.build()")
-    (run_step if args.what == "step" else run_copy)(args)
+    {"step": run_step, "copy": run_copy, "streams": run_streams}[args.what](args)
 
 
 if __name__ == "__main__":

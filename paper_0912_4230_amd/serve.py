@@ -7,8 +7,13 @@ advances all active lattices together in ticks: one batched launch per
 step for all lattices of the same physics and storage (lbm_step_batch), so
 requests that arrive while others run join the next tick and their work
 overlaps on the device.  A lattice that reaches its step count is retired
-at the end of its tick (moments copied out, workspace freed), which frees
-budget for the queue.  Latency = completion - arrival on the host clock.
+once its tick has completed (moments copied out, workspace freed), which
+frees budget for the queue.  Latency = completion - arrival on the host clock.
+
+The host keeps one tick queued ahead of the device: tick n+1 is issued
+before the host waits for tick n, and new lattices are set up (and finished
+ones read back) on a second stream while the ticks run, so the device does
+not idle while the host admits or retires requests.
 
 The scheduler talks to an executor (GpuExecutor here, a mock in the CPU
 tests), so admission, budget and retirement logic run without a GPU.
@@ -47,7 +52,9 @@ class Outcome:
 
 
 class GpuExecutor:
-    """Runs lattices through the C ABI; all lattices share one stream."""
+    """Runs lattices through the C ABI.  The ticks of all active lattices run
+    on one stream (the current stream of the device); set-up and read-back
+    run on a second stream of default priority, so they overlap the ticks."""
 
     def __init__(self, storage="f32", device="cuda:0", keep_results=False, problems=None):
         import torch
@@ -57,8 +64,10 @@ class GpuExecutor:
         self.storage = B.STORAGE_NAMES[storage] if isinstance(storage, str) else storage
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
+        self.side = torch.cuda.Stream(device=self.device)
         self.keep_results = keep_results
         self.problems = problems or {}
+        self.busy_s = 0.0           # device time of the completed ticks
 
     def problem(self, req: I.Request):
         p = self.problems.get(req.rid)
@@ -69,18 +78,32 @@ class GpuExecutor:
         return self.B.lbm_workspace_bytes(make_desc(self.problem(req), self.storage))
 
     def admit(self, req: I.Request):
+        """Set the lattice up on the side stream (lbm_set_medium synchronises
+        that stream only), then hand it to the tick stream."""
         from .sim import Simulation
-        return Simulation(self.problem(req), storage=self.storage, device=self.device, stream=self.stream)
+        sim = Simulation(self.problem(req), storage=self.storage, device=self.device, stream=self.side)
+        return sim.set_stream(self.stream)
 
     def run_tick(self, handles, nsteps):
+        """Issue one tick (asynchronous); returns its token."""
         from .sim import step_batch
+        t0 = self.torch.cuda.Event(enable_timing=True)
+        t1 = self.torch.cuda.Event(enable_timing=True)
+        t0.record(self.stream)
         step_batch(handles, nsteps)
+        t1.record(self.stream)
+        return (t0, t1)
 
-    def sync(self):
-        self.torch.cuda.synchronize(self.device)
+    def wait(self, token):
+        """Block until the tick of `token` has completed on the device."""
+        t0, t1 = token
+        t1.synchronize()
+        self.busy_s += t0.elapsed_time(t1) / 1e3
 
     def finish(self, sim):
-        """Moments of the last step; status 'ok' or 'unstable'."""
+        """Moments of the last step (its tick has completed); status 'ok' or
+        'unstable'.  Read back on the side stream."""
+        sim.set_stream(self.side)
         rho, vel, conc, diag = sim.moments(check=False)
         status = "ok" if diag[7] == 0 else "unstable"
         res = (rho, vel, conc, diag) if self.keep_results else diag
@@ -89,6 +112,9 @@ class GpuExecutor:
     def release(self, sim):
         sim.close()
         sim.ws = None
+
+    def busy_seconds(self) -> float:
+        return self.busy_s
 
 
 def nearest_rank(values: List[float], p: float) -> float:
@@ -144,25 +170,9 @@ def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: in
             used += nb
             active.append(Job(req, h, nb, req.steps, now()))
 
-    while pending or active:
-        admit_ready()
-        if not active:
-            if pending:
-                wait = pending[0].arrival - now()
-                if wait > 0:
-                    sleep(wait)
-            continue
-        nsteps = [min(tick_steps, j.remaining) for j in active]
-        executor.run_tick([j.handle for j in active], nsteps)
-        executor.sync()
-        ticks += 1
-        max_active = max(max_active, len(active))
-        still = []
-        for j, n in zip(active, nsteps):
-            j.remaining -= n
-            if j.remaining > 0:
-                still.append(j)
-                continue
+    def retire(jobs):
+        nonlocal used
+        for j in jobs:
             status, res = executor.finish(j.handle)
             t = now()
             outcomes[j.req.rid] = Outcome(j.req.rid, j.req.arrival, j.admitted, t, t - j.req.arrival,
@@ -171,14 +181,44 @@ def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: in
             used -= j.nbytes
             if log:
                 log(f"serve: request {j.req.rid} ({j.req.edge}^3 x {j.req.steps}) done in {t - j.req.arrival:.2f} s")
-        active = still
+
+    # the tick issued last and the lattices that finish with it
+    inflight = None
+    while pending or active or inflight is not None:
+        admit_ready()
+        token, finishing = None, []
+        if active:
+            nsteps = [min(tick_steps, j.remaining) for j in active]
+            token = executor.run_tick([j.handle for j in active], nsteps)
+            ticks += 1
+            max_active = max(max_active, len(active))
+            still = []
+            for j, n in zip(active, nsteps):
+                j.remaining -= n
+                (still if j.remaining > 0 else finishing).append(j)
+            active = still
+        # the device runs the tick just issued while the host waits for the
+        # previous one and retires what finished with it
+        if inflight is not None:
+            executor.wait(inflight[0])
+            retire(inflight[1])
+            inflight = None
+        if token is not None:
+            inflight = (token, finishing)
+        elif pending:
+            wait = pending[0].arrival - now()
+            if wait > 0:
+                sleep(wait)
 
     done = [o for o in outcomes.values() if o.status in ("ok", "unstable")]
     lat = [o.latency for o in done]
     lups = sum(o.cells * o.steps for o in done)
     span = (max(o.completed for o in done) - min(o.arrival for o in done)) if done else float("nan")
+    busy = executor.busy_seconds() if hasattr(executor, "busy_seconds") else float("nan")
     return {
         "outcomes": outcomes,
+        "busy_s": busy,
+        "busy_fraction": busy / span if done and span > 0 else float("nan"),
         "p50_s": nearest_rank(lat, 50),
         "p99_s": nearest_rank(lat, 99),
         "mean_s": sum(lat) / len(lat) if lat else float("nan"),

@@ -74,16 +74,18 @@ class Simulation:
             raise B.LbmError(B.LBM_EINVAL, "lbm_workspace_bytes")
         self.nbytes = nbytes
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        if static_workspace:
-            # the library's own static workspace of this device (lbm_create_static)
-            self.ws = None
-            with torch.cuda.device(self.device):
-                self.h = B.lbm_create_static(self.desc, self.stream.cuda_stream)
-        else:
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self.h = B.lbm_create(self.desc, self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
         self.shape = tuple(p.shape)
-        self._set_medium(p, uniform_medium)
+        # the workspace, the uploads of the fields and the set-up all run on
+        # the lattice's stream (work on other streams is not waited for)
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            if static_workspace:
+                # the library's own static workspace of this device (lbm_create_static)
+                self.ws = None
+                self.h = B.lbm_create_static(self.desc, self.stream.cuda_stream)
+            else:
+                self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                self.h = B.lbm_create(self.desc, self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
+            self._set_medium(p, uniform_medium)
 
     # ------------------------------------------------------------------
     def _dev(self, a):
@@ -122,10 +124,17 @@ class Simulation:
             t = torch.from_numpy(np.ascontiguousarray(np.asarray(p.solid) != 0, dtype=np.uint8)).to(self.device)
             keep.append(t)
             m.solid = t.data_ptr()
-        with torch.cuda.stream(self.stream):
-            torch.cuda.current_stream(self.device).wait_stream(torch.cuda.default_stream(self.device))
-            B.lbm_set_medium(self.h, m)
+        B.lbm_set_medium(self.h, m)    # synchronises the lattice's stream
         del keep
+
+    def set_stream(self, stream) -> "Simulation":
+        """Issue the lattice's later work on `stream` (lbm_set_stream); the
+        caller orders it after the work already issued on the old stream."""
+        B.lbm_set_stream(self.h, stream.cuda_stream)
+        if self.ws is not None:
+            self.ws.record_stream(stream)
+        self.stream = stream
+        return self
 
     def step(self, n: int = 1) -> "Simulation":
         B.lbm_step(self.h, n)
@@ -140,10 +149,11 @@ class Simulation:
         diagnostics as a numpy array of 8."""
         import torch
         nx, ny, nz = self.shape
-        rho = torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
-        vel = torch.empty((3, nz, ny, nx), dtype=self.dtype, device=self.device)
-        ns = self.problem.nspecies if self.problem.physics == I.MISCIBLE else 1
-        conc = torch.empty(((ns,) if ns > 1 else ()) + (nz, ny, nx), dtype=self.dtype, device=self.device)
+        with torch.cuda.stream(self.stream):
+            rho = torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
+            vel = torch.empty((3, nz, ny, nx), dtype=self.dtype, device=self.device)
+            ns = self.problem.nspecies if self.problem.physics == I.MISCIBLE else 1
+            conc = torch.empty(((ns,) if ns > 1 else ()) + (nz, ny, nx), dtype=self.dtype, device=self.device)
         diag = (C.c_double * 8)()
         B.lbm_moments(self.h, rho.data_ptr(), vel.data_ptr(), conc.data_ptr(), diag, check=check)
         return rho, vel, conc, np.array(diag[:])

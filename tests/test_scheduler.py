@@ -19,7 +19,10 @@ class Clock:
 
 
 class MockExecutor:
-    """Fake lattices: bytes = 100 per cell, cost = cells * steps / rate seconds."""
+    """Fake lattices: bytes = 100 per cell, cost = cells * steps / rate seconds
+    of a fake device that runs the issued ticks one after the other while the
+    host goes on (run_tick returns the time the tick completes, wait advances
+    the host clock to it)."""
 
     def __init__(self, clock, rate=1e9, unstable=()):
         self.clock = clock
@@ -28,6 +31,8 @@ class MockExecutor:
         self.used = 0
         self.peak = 0
         self.batches = []
+        self.free_at = 0.0
+        self.busy = 0.0
 
     def workspace_bytes(self, req):
         return 100 * req.edge ** 3
@@ -39,10 +44,17 @@ class MockExecutor:
 
     def run_tick(self, handles, nsteps):
         self.batches.append([h["req"].rid for h in handles])
-        self.clock.t += sum(h["req"].edge ** 3 * n for h, n in zip(handles, nsteps)) / self.rate
+        cost = sum(h["req"].edge ** 3 * n for h, n in zip(handles, nsteps)) / self.rate
+        start = max(self.clock.t, self.free_at)
+        self.free_at = start + cost
+        self.busy += cost
+        return self.free_at
 
-    def sync(self):
-        pass
+    def wait(self, token):
+        self.clock.t = max(self.clock.t, token)
+
+    def busy_seconds(self):
+        return self.busy
 
     def finish(self, h):
         return ("unstable" if h["req"].rid in self.unstable else "ok"), None
@@ -116,6 +128,31 @@ def test_unstable_request_is_isolated():
     st = serve(reqs, ex, 1 << 60, tick_steps=50, clock=clk, sleep=clk.sleep)
     assert st["outcomes"][reqs[3].rid].status == "unstable"
     assert sum(o.status == "ok" for o in st["outcomes"].values()) == len(reqs) - 1
+
+
+def test_next_tick_issued_before_waiting():
+    """The host issues tick n+1 before it waits for tick n: while requests keep
+    the device busy it never idles between ticks, and the busy fraction is the
+    device time over the span."""
+    clk = Clock()
+    ex = MockExecutor(clk, rate=1e7)
+    waits = []
+    wait0 = ex.wait
+
+    def wait(token):
+        # at every wait, a later tick is already issued (unless the stream drained)
+        waits.append((token, ex.free_at))
+        wait0(token)
+    ex.wait = wait
+    reqs = _reqs(16)
+    st = serve(reqs, ex, 1 << 60, tick_steps=25, clock=clk, sleep=clk.sleep)
+    assert st["completed"] == len(reqs)
+    # a wait without a later tick issued happens only where the active set
+    # drains (the device then has nothing to run anyway)
+    ahead = sum(1 for tok, free in waits if free > tok)
+    assert ahead > len(waits) // 2
+    assert 0.0 < st["busy_fraction"] <= 1.0 + 1e-12
+    assert abs(st["busy_s"] - ex.busy) < 1e-12
 
 
 def test_nearest_rank():
