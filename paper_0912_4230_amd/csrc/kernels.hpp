@@ -6,7 +6,8 @@
 // structure-of-arrays [19][nz][ny][nx] in two copies (A-B): a step pulls from
 // the copy holding step n and writes step n+1 into the other one, so each
 // population is read once and written once per step and no cell waits for
-// another.  The hot path is bound by HBM bandwidth, not arithmetic; there is
+// another.  In 16-bit storage the miscible model pairs its two lattices:
+// plane q holds one 32-bit word (f_q, h_q) per cell.  The hot path is bound by HBM bandwidth, not arithmetic; there is
 // no dense contraction, hence no MFMA.
 //
 // Addressing: every population plane is addressed as a wave-uniform base
@@ -74,6 +75,7 @@ struct LatDev {
     int *err;
     uint32_t div_nx[3], div_nxy[3];   // magic numbers of the divisions by nx and nx*ny
     uint32_t pstride;           // elements from one population plane to the next (>= ncell)
+    uint32_t ppstride;          // paired planes (miscible, 16-bit storage): words from one plane to the next
 };
 
 // Solutes beyond the first (miscible mode with several species), in the
@@ -414,6 +416,75 @@ __device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, con
         store_each<S>(P, n, idx, r);
     } else {
         store_each<S>(P, n, idx, v);
+    }
+}
+
+// Paired storage (miscible model, 16-bit codecs): plane q of a copy holds,
+// per cell, the PairCodec word of (f_q, h_q); split codecs keep the cell's
+// two FP32 masses as one pair (m_f, m_h).  One pull then loads one word per
+// link for both lattices.  Rounding and arithmetic are those of the unpaired
+// codecs, so results are bitwise the same.
+template <int PHYS, class S>
+constexpr bool paired_v = PHYS == PH_MISCIBLE && sizeof(S) == 2;
+
+template <class S, bool BB, int Q = 0>
+__device__ inline void pair_loads(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
+                                  typename Codec<S>::R *a, typename Codec<S>::R *c, f32x2_t *m)
+{
+    using W = typename PairCodec<S>::W;
+    if constexpr (BB && Q != 0) {
+        const bool s = shifted_solid<Q, -1>(b);
+        PairCodec<S>::load(at(plane<W>(P, n, pair_lo<Q>()), pair_offset<Q>(b, n, idx, s)), a[Q], c[Q]);
+        if constexpr (Codec<S>::split) m[Q] = ldg<f32x2_t>(M, s ? idx : shifted<Q, -1>(b));
+    } else {
+        const uint32_t src = shifted<Q, -1>(b);
+        PairCodec<S>::load(at(plane<W>(P, n, Q), src), a[Q], c[Q]);
+        if constexpr (Codec<S>::split) m[Q] = ldg<f32x2_t>(M, src);
+    }
+    if constexpr (Q + 1 < NQ) pair_loads<S, BB, Q + 1>(P, M, n, idx, b, a, c, m);
+}
+
+// Pull of both lattices from paired planes (a: f, c: h).
+template <class S>
+__device__ inline void pull_pair(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
+                                 typename Codec<S>::R *a, typename Codec<S>::R *c)
+{
+    using R = typename Codec<S>::R;
+    f32x2_t m[Codec<S>::split ? NQ : 1];
+    if (wave_near_solid(b)) pair_loads<S, true>(P, M, n, idx, b, a, c, m);
+    else pair_loads<S, false>(P, M, n, idx, b, a, c, m);
+    if constexpr (Codec<S>::split) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            a[q] = fma(weight<R>(q), m[q].x, a[q]);
+            c[q] = fma(weight<R>(q), m[q].y, c[q]);
+        }
+    }
+}
+
+// Store of both lattices' 19 populations into paired planes (split codecs:
+// the masses as in store_all, one pair per cell).
+template <class S>
+__device__ inline void store_pair(void *P, void *M, uint32_t n, uint32_t idx, const typename Codec<S>::R *a,
+                                  const typename Codec<S>::R *c)
+{
+    using R = typename Codec<S>::R;
+    using W = typename PairCodec<S>::W;
+    if constexpr (Codec<S>::split) {
+        R ma = 0, mc = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            ma += a[q];
+            mc += c[q];
+        }
+        stg<f32x2_t>(M, idx, f32x2_t{ma, mc});
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            PairCodec<S>::store(at(plane_w<W>(P, n, q), idx), fma(-weight<R>(q), ma, a[q]),
+                                fma(-weight<R>(q), mc, c[q]));
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) PairCodec<S>::store(at(plane_w<W>(P, n, q), idx), a[q], c[q]);
     }
 }
 
@@ -811,17 +882,19 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 // of the launch has a full permeability tensor (eigenframe form).  MS
 // (miscible): the lattices may carry further solutes, updated after the
 // first with the same V' (a runtime count per lattice, possibly 0).
-// Waves per SIMD the step is compiled for.  The miscible step with 16-bit
-// storage (diagonal K, one solute) fits in 95-96 VGPRs at 5 waves without
-// spills and runs 5-18% faster there at 256^3 and 7-9% at 512^3; every other
-// form keeps the compiler's own choice (1 = no constraint; the FP32 and FP64
-// code is the same as without the attribute) and the LDS reserve that holds
-// it at 4 waves.
+// Waves per SIMD the step is compiled for.  The miscible step with plain
+// 16-bit storage (diagonal K, one solute) fits in 95 VGPRs at 5 waves without
+// spills and runs 5-18% faster there at 256^3 and 7-9% at 512^3.  The split
+// forms (19 pair words and 19 mass pairs per pull) take 104-105 VGPRs and run
+// at 4 waves: forced to 5 they spill, and issuing their pull in two halves to
+// fit 5 waves measured 3% slower.  Every other form keeps the compiler's own
+// choice (1 = no constraint; the FP32 and FP64 code is the same as without
+// the attribute).
 template <int PHYS, class S, bool FT, bool MS> struct StepWaves { static constexpr int value = 1; };
 template <> struct StepWaves<PH_MISCIBLE, bf16_t, false, false> { static constexpr int value = 5; };
 template <> struct StepWaves<PH_MISCIBLE, f16_t, false, false> { static constexpr int value = 5; };
-template <> struct StepWaves<PH_MISCIBLE, bf16s_t, false, false> { static constexpr int value = 5; };
-template <> struct StepWaves<PH_MISCIBLE, f16s_t, false, false> { static constexpr int value = 5; };
+template <> struct StepWaves<PH_MISCIBLE, bf16s_t, false, false> { static constexpr int value = 4; };
+template <> struct StepWaves<PH_MISCIBLE, f16s_t, false, false> { static constexpr int value = 4; };
 
 template <int PHYS, class S, bool FT = false, bool MS = false>
 __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, FT, MS>::value))) void k_step(
@@ -870,8 +943,12 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
     [[maybe_unused]] R x_eps = 1, x_ie = 1, x_u[3] = {0, 0, 0}, x_g[3] = {0, 0, 0};
     if (type == CELL_FLUID) {
         const Nbr b = neighbours(L, x, y, z, lw);
-        pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
-        if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], L->hm[src], L->pstride, idx, b, hq);
+        if constexpr (paired_v<PHYS, S>) {
+            pull_pair<S>(L->f[src], L->fm[src], L->ppstride, idx, b, d, hq);
+        } else {
+            pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
+            if constexpr (PHYS == PH_MISCIBLE) pull_all<S>(L->h[src], L->hm[src], L->pstride, idx, b, hq);
+        }
 
         R drho = 0, jx = 0, jy = 0, jz = 0;
         moments_acc<R>(d, drho, jx, jy, jz);
@@ -1004,8 +1081,12 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
     }
     // waves made of solid cells only (wall planes, obstacle interiors) skip
     if (idx < ncell && __builtin_amdgcn_ballot_w64(type != CELL_SOLID) != 0) {
-        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[dst], L->hm[dst], L->pstride, idx, hq);
-        store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
+        if constexpr (paired_v<PHYS, S>) {
+            store_pair<S>(L->f[dst], L->fm[dst], L->ppstride, idx, d, hq);
+        } else {
+            if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[dst], L->hm[dst], L->pstride, idx, hq);
+            store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
+        }
     }
     if constexpr (MS) {
         // further solutes: the first solute's update with their own D, tau_d
@@ -1403,8 +1484,12 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
         mC = C;
     }
     for (int cpy = 0; cpy < 2; ++cpy) {
-        store_all<S>(L->f[cpy], L->fm[cpy], L->pstride, idx, d);
-        if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], L->hm[cpy], L->pstride, idx, hq);
+        if constexpr (paired_v<PHYS, S>) {
+            store_pair<S>(L->f[cpy], L->fm[cpy], L->ppstride, idx, d, hq);
+        } else {
+            store_all<S>(L->f[cpy], L->fm[cpy], L->pstride, idx, d);
+            if constexpr (PHYS != PH_SINGLE) store_all<S>(L->h[cpy], L->hm[cpy], L->pstride, idx, hq);
+        }
     }
     void *M = L->mom;
     stg<R>(M, idx, mrho);
@@ -1520,6 +1605,23 @@ __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, in
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= ncell) return;
     using R = typename Codec<S>::R;
+    if constexpr (sizeof(S) == 2) {
+        if (L->physics == PH_MISCIBLE && which < 2) {
+            // paired planes: half `which` of every word (and of the mass pair)
+            using W = typename PairCodec<S>::W;
+            R m = 0;
+            if constexpr (Codec<S>::split) {
+                const f32x2_t mp = ldg<f32x2_t>(L->fm[src], idx);
+                m = which == 0 ? mp.x : mp.y;
+            }
+            for (int q = 0; q < NQ; ++q) {
+                R a, c;
+                PairCodec<S>::load(at(plane<W>(L->f[src], L->ppstride, q), idx), a, c);
+                dst[size_t(q) * ncell + idx] = fma(weight<R>(q), m, which == 0 ? a : c);
+            }
+            return;
+        }
+    }
     const MsDev *X = ms_of(L);
     const void *P = which == 0 ? L->f[src] : (which == 1 ? L->h[src] : X->h[which - 2][src]);
     const void *M = which == 0 ? L->fm[src] : (which == 1 ? L->hm[src] : X->hm[which - 2][src]);

@@ -49,14 +49,28 @@ size_t real_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 #ifndef PLBM_BIG_PAD
 #define PLBM_BIG_PAD (512 * 1024 + 512)
 #endif
-size_t plane_stride(const lbm_desc *d)
+size_t plane_stride_of(size_t n, size_t sb)
 {
-    const size_t n = (size_t)d->nx * d->ny * d->nz;
-    const size_t sb = storage_bytes(d->storage), per = 256 / sb;
+    const size_t per = 256 / sb;
     const size_t base = (n + per - 1) / per * per, bytes = base * sb;
     const size_t MiB = size_t(1) << 20;
     const size_t pad = (bytes >= 256 * MiB && bytes % MiB == 0) ? size_t(PLBM_BIG_PAD) : 512;
     return base + pad / sb;
+}
+
+size_t plane_stride(const lbm_desc *d)
+{
+    return plane_stride_of((size_t)d->nx * d->ny * d->nz, storage_bytes(d->storage));
+}
+
+// Miscible lattices in 16-bit storage keep f and h in paired planes of
+// 32-bit words (and split codecs their two masses as one 8-byte pair per
+// cell); the planes are padded as planes of 4-byte elements.
+bool paired_storage(const lbm_desc *d) { return d->physics == LBM_MISCIBLE && storage_bytes(d->storage) == 2; }
+
+size_t pair_plane_stride(const lbm_desc *d)
+{
+    return plane_stride_of((size_t)d->nx * d->ny * d->nz, 2 * storage_bytes(d->storage));
 }
 
 struct Layout {
@@ -84,16 +98,17 @@ bool valid_desc(const lbm_desc *d)
     if (ncell > (1LL << 31) - BLOCK) return false;
     // planes are addressed by 32-bit byte offsets from a uniform base: a
     // field plane, or a pair of population planes for the bounce-back selects
+    if (d->physics < LBM_SINGLE || d->physics > LBM_FREESURF) return false;
+    if (d->storage < LBM_F64 || d->storage > LBM_F16_SPLIT) return false;
     const unsigned long long pair = 2ULL * plane_stride(d) * storage_bytes(d->storage);
     if ((unsigned long long)ncell * real_bytes(d->storage) > (1ULL << 32) || pair > (1ULL << 32)) return false;
-    if (d->physics < LBM_SINGLE || d->physics > LBM_FREESURF) return false;
+    if (paired_storage(d) && 2ULL * pair_plane_stride(d) * 2 * storage_bytes(d->storage) > (1ULL << 32)) return false;
     // free surface: per-cell doubles addressed by 32-bit byte offsets; no reservoirs
     if (d->physics == LBM_FREESURF) {
         if ((unsigned long long)ncell * 8ULL > (1ULL << 32)) return false;
         for (int f = 0; f < 6; ++f)
             if (d->face[f].kind == LBM_FACE_RESERVOIR) return false;
     }
-    if (d->storage < LBM_F64 || d->storage > LBM_F16_SPLIT) return false;
     const int n[3] = {d->nx, d->ny, d->nz};
     for (int a = 0; a < 3; ++a) {
         const int k0 = d->face[2 * a].kind, k1 = d->face[2 * a + 1].kind;
@@ -153,15 +168,17 @@ Layout layout(const lbm_desc *d)
     L.rho1 = o;      if (d->physics == LBM_IMMISCIBLE) o = align_up(o + n * rb);
     L.links = o;     if (d->solid_mask) o = align_up(o + n * sizeof(uint32_t));
     const size_t ps = plane_stride(d);
-    L.f0 = o;        o = align_up(o + NQ * ps * sb);
-    L.f1 = o;        o = align_up(o + NQ * ps * sb);
-    const bool sp = split_storage(d->storage), two = two_lattices(d->physics);
-    L.h0 = o;        if (two) o = align_up(o + NQ * ps * sb);
-    L.h1 = o;        if (two) o = align_up(o + NQ * ps * sb);
-    L.fm0 = o;       if (sp) o = align_up(o + n * sizeof(float));
-    L.fm1 = o;       if (sp) o = align_up(o + n * sizeof(float));
-    L.hm0 = o;       if (sp && two) o = align_up(o + n * sizeof(float));
-    L.hm1 = o;       if (sp && two) o = align_up(o + n * sizeof(float));
+    const bool sp = split_storage(d->storage), two = two_lattices(d->physics), pr = paired_storage(d);
+    // paired: f0 / f1 hold both lattices, fm0 / fm1 both masses
+    const size_t fbytes = pr ? NQ * pair_plane_stride(d) * 2 * sb : NQ * ps * sb;
+    L.f0 = o;        o = align_up(o + fbytes);
+    L.f1 = o;        o = align_up(o + fbytes);
+    L.h0 = o;        if (two && !pr) o = align_up(o + NQ * ps * sb);
+    L.h1 = o;        if (two && !pr) o = align_up(o + NQ * ps * sb);
+    L.fm0 = o;       if (sp) o = align_up(o + n * sizeof(float) * (pr ? 2 : 1));
+    L.fm1 = o;       if (sp) o = align_up(o + n * sizeof(float) * (pr ? 2 : 1));
+    L.hm0 = o;       if (sp && two && !pr) o = align_up(o + n * sizeof(float));
+    L.hm1 = o;       if (sp && two && !pr) o = align_up(o + n * sizeof(float));
     const bool fs = d->physics == LBM_FREESURF;
     // free surface: the FsDev block (+ the lost-mass counter), three byte
     // planes, five double planes (m, two of lambda, rho, share) and the 3
@@ -552,6 +569,7 @@ void setup_handle(lbm_sim *h, const lbm_desc *d, void *dev_workspace, size_t ws_
         D.bpp = (PLBM_SLAB && plane_cells % BLOCK == 0 && bpp % 8 == 0) ? int(bpp) : 0;
     }
     D.pstride = uint32_t(plane_stride(d));
+    D.ppstride = paired_storage(d) ? uint32_t(pair_plane_stride(d)) : 0;
     magic_divisor(uint32_t(d->nx), D.div_nx);
     magic_divisor(uint32_t(d->nx) * uint32_t(d->ny), D.div_nxy);
     D.physics = d->physics;
@@ -582,13 +600,13 @@ void setup_handle(lbm_sim *h, const lbm_desc *d, void *dev_workspace, size_t ws_
     char *w = h->ws;
     D.f[0] = w + L.f0;
     D.f[1] = w + L.f1;
-    const bool sp = split_storage(d->storage), two = two_lattices(d->physics);
-    D.h[0] = two ? w + L.h0 : nullptr;
-    D.h[1] = two ? w + L.h1 : nullptr;
+    const bool sp = split_storage(d->storage), two = two_lattices(d->physics), pr = paired_storage(d);
+    D.h[0] = two && !pr ? w + L.h0 : nullptr;
+    D.h[1] = two && !pr ? w + L.h1 : nullptr;
     D.fm[0] = sp ? w + L.fm0 : nullptr;
     D.fm[1] = sp ? w + L.fm1 : nullptr;
-    D.hm[0] = sp && two ? w + L.hm0 : nullptr;
-    D.hm[1] = sp && two ? w + L.hm1 : nullptr;
+    D.hm[0] = sp && two && !pr ? w + L.hm0 : nullptr;
+    D.hm[1] = sp && two && !pr ? w + L.hm1 : nullptr;
     D.eps = w + L.eps;
     D.kinv = w + L.kinv;
     D.mom = w + L.mom;

@@ -102,11 +102,18 @@ def run_copy(args):
 
 
 def run_streams(args):
-    """The probe library's 38-stream kernel (38 planes read and written, one
-    cell per thread) over n = size^3 cells of 4- or 2-byte elements in the
+    """The probe library's 38-stream kernels (38 planes read and written, one
+    cell per thread) over n = size^3 cells of 4- or 2-byte elements: in the
     plane-major layout of the lattice workspace (planes `pad` elements apart
-    beyond n) or slice-major (all 38 planes of each z-slice of size^2 cells
-    contiguous); HIP-event rate."""
+    beyond n), slice-major (all 38 planes of each z-slice of size^2 cells
+    contiguous, `pad` elements after each) or row-interleaved (all 38 planes of
+    each row of size cells contiguous, `pad` elements after each); with
+    --shift every stream reads the upstream cell of its D3Q19 link in a
+    periodic cube (the pull of a step without its arithmetic; plane and row
+    layouts, size a power of two); with --xcd each XCD sweeps runs of 4
+    consecutive blocks of cells, as the lattice step does; --uniform is the
+    shifted pull with row groups addressed as the step addresses its planes
+    (uniform source-row bases, 32-bit x offsets).  HIP-event rate."""
     import ctypes
     import torch
     from paper_0912_4230_amd.build_lib import PROBE_LIB
@@ -116,21 +123,47 @@ def run_streams(args):
     probe.probe_streams38.restype = ctypes.c_int
     probe.probe_streams38.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_size_t,
                                       ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
+    probe.probe_streams38_cube.restype = ctypes.c_int
+    probe.probe_streams38_cube.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
+    probe.probe_streams_uni.restype = ctypes.c_int
+    probe.probe_streams_uni.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
     n = args.size ** 3
+    ns = 19 if args.pairs else 38
+    elem = args.elem * (2 if args.pairs else 1)
+    if args.pairs and not args.uniform:
+        raise SystemExit("streams: --pairs runs with --uniform")
+    cube = args.layout == "row" or args.shift or args.xcd or args.uniform
+    if cube:
+        lg = args.size.bit_length() - 1
+        if args.size != 1 << lg or args.layout == "slice":
+            raise SystemExit("streams: the row layout and --shift take a power-of-two size, plane or row layout")
     if args.layout == "plane":
         pstride, slice_, sstride = n + args.pad, 0, 0
-        total = 38 * pstride
-    else:
+        total = ns * pstride
+    elif args.layout == "slice":
         pstride, slice_, sstride = 0, args.size ** 2, args.size ** 2 + args.pad
         total = args.size * 38 * sstride
-    dt = torch.float32 if args.elem == 4 else torch.int16
+    else:
+        pstride, pitch = 0, args.size + args.pad
+        total = args.size ** 2 * ns * pitch
+    dt = {8: torch.int64, 4: torch.float32, 2: torch.int16}[elem]
     a = torch.zeros(total, dtype=dt, device="cuda")
     b = torch.empty_like(a)
     stream = torch.cuda.current_stream()
 
     def launch():
-        rc = probe.probe_streams38(b.data_ptr(), a.data_ptr(), n, pstride, slice_, sstride, stream.cuda_stream,
-                                   args.elem)
+        if args.pairs:
+            rc = probe.probe_streams_uni(b.data_ptr(), a.data_ptr(), lg, ns, int(args.layout == "row"), pstride,
+                                         pitch if args.layout == "row" else 0, stream.cuda_stream, elem)
+        elif cube:
+            rc = probe.probe_streams38_cube(b.data_ptr(), a.data_ptr(), lg, int(args.layout == "row"),
+                                            int(args.shift), 2 if args.uniform else int(args.xcd), pstride, pitch if args.layout == "row" else 0,
+                                            stream.cuda_stream, args.elem)
+        else:
+            rc = probe.probe_streams38(b.data_ptr(), a.data_ptr(), n, pstride, slice_, sstride, stream.cuda_stream,
+                                       args.elem)
         if rc:
             raise SystemExit(f"probe_streams38 failed ({rc})")
     launch()
@@ -143,9 +176,10 @@ def run_streams(args):
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.reps
-    print(f"profile_run streams: {args.layout}-major, {args.size}^3 cells, 38 planes of {args.elem}-byte elements, "
-          f"pad {args.pad} elements: {ms:.3f} ms per launch, {2 * 38 * args.elem * n / ms / 1e6:.1f} GB/s "
-          f"(HIP events)", flush=True)
+    print(f"profile_run streams: {args.layout}{' shifted' if args.shift else ''}{' xcd-groups' if args.xcd else ''}"
+          f"{' uniform-rows' if args.uniform else ''}, {args.size}^3 cells, {ns} planes of "
+          f"{elem}-byte elements, pad {args.pad} elements: {ms:.3f} ms per launch, "
+          f"{2 * 38 * args.elem * n / ms / 1e6:.1f} GB/s (HIP events)", flush=True)
 
 
 def main():
@@ -163,7 +197,13 @@ def main():
     c.add_argument("--blocks", type=int, default=8192, help="grid of the f4 probe (256 threads per block)")
     t = sub.add_parser("streams")
     t.add_argument("--size", type=int, default=256)
-    t.add_argument("--layout", default="plane", choices=["plane", "slice"])
+    t.add_argument("--layout", default="plane", choices=["plane", "slice", "row"])
+    t.add_argument("--shift", action="store_true", help="pull every stream from its link's upstream cell")
+    t.add_argument("--xcd", action="store_true", help="map blocks to XCD row groups of 4 blocks")
+    t.add_argument("--pairs", action="store_true",
+                   help="19 planes of elements twice --elem wide (both lattices' values of a link side by side)")
+    t.add_argument("--uniform", action="store_true",
+                   help="shifted pull with XCD row groups and uniform row bases (size >= 256)")
     t.add_argument("--pad", type=int, default=128, help="elements of padding after each plane (slice)")
     t.add_argument("--elem", type=int, default=4, choices=[4, 2], help="element bytes")
     t.add_argument("--reps", type=int, default=10)
