@@ -463,6 +463,61 @@ __device__ inline bool any_byte(const u32x4 &v) { return (v.x | v.y | v.z | v.w)
 // the cell empties after all: flagged EMPTY and not kept by a filling neighbour
 __device__ inline bool empties(int w1, int w2) { return w1 == FS_EMPTY && !(w2 & FS_KEEP); }
 
+// Position of the n-th set bit (from 0) of v, n < popcount(v), by halving.
+__host__ __device__ inline int nth_set_bit(uint64_t v, uint32_t n)
+{
+    int pos = 0;
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint32_t c = uint32_t(__builtin_popcountll((v >> pos) & ((uint64_t(1) << w) - 1)));
+        if (n >= c) {
+            n -= c;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+// The work of a wave's class pass: lane l covers the FS_CPT cells from
+// base(l) = wbase + FS_CPT l and marks item k (cell base(l) + k) in bit k of
+// its mask.  The items are dealt to the lanes in rounds of 64 (k major, lane
+// minor) and fn(idx) runs on the lane an item is dealt to, so the wave waits
+// for ceil(items / 64) chains of dependent neighbour loads rather than up to
+// FS_CPT chains one after the other on the lane that found them.  Cells are
+// independent within a pass, so the dealing changes no result.  Every lane
+// of the wave must call it.
+template <class Fn>
+__device__ inline void for_items(uint32_t mask, uint32_t base, Fn &&fn)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t wbase = base - uint32_t(FS_CPT * lane);
+    uint64_t B[FS_CPT];
+    uint32_t start[FS_CPT + 1];
+    start[0] = 0;
+#pragma unroll
+    for (int k = 0; k < FS_CPT; ++k) {
+        B[k] = __builtin_amdgcn_ballot_w64(((mask >> k) & 1u) != 0u);
+        start[k + 1] = start[k] + uint32_t(__builtin_popcountll(B[k]));
+    }
+    const uint32_t total = start[FS_CPT];
+    for (uint32_t r = 0; r < total; r += 64) {
+        const uint32_t i = r + uint32_t(lane);
+        if (i >= total) continue;
+        // the item's k: the last k with start[k] <= i (B[k] is then not empty)
+        int k = 0;
+        uint64_t bits = B[0];
+        uint32_t n = i;
+#pragma unroll
+        for (int kk = 1; kk < FS_CPT; ++kk) {
+            if (i >= start[kk]) {
+                k = kk;
+                bits = B[kk];
+                n = i - start[kk];
+            }
+        }
+        fn(wbase + uint32_t(FS_CPT * nth_set_bit(bits, n) + k));
+    }
+}
+
 __device__ inline Nbr nbr_of(const LatDev *L, uint32_t idx)
 {
     int x, y, z;
@@ -475,9 +530,9 @@ __device__ inline Nbr nbr_of(const LatDev *L, uint32_t idx)
 __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
 {
     const FsTile t = fs_tile(a);
-    if (t.base >= t.ncell) return;
     const FsDev *__restrict__ F = t.F;
-    {
+    uint32_t mask = 0;
+    if (t.base < t.ncell) {
         // the launch-order list pass 1 has just used serves the next step
         // again: unlist its rows (the count is cleared by the next pass)
         const int src = t.flags & 1;
@@ -486,12 +541,13 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
             const uint32_t r = ldg<uint32_t>(F->hlist[src], tn);
             if (r < nrow) stg<uint32_t>(F->hpos[src], r, 0u);
         }
+        const u32x4 f = ld16(F->w1, t.base);
+        if (any_byte(f))
+            for (int k = 0; k < FS_CPT; ++k)
+                if (t.base + k < t.ncell && byte_of(f, k) == FS_FILL) mask |= 1u << k;
     }
-    const u32x4 f = ld16(F->w1, t.base);
-    if (!any_byte(f)) return;
-    for (int k = 0; k < FS_CPT; ++k) {
-        const uint32_t idx = t.base + k;
-        if (idx >= t.ncell || byte_of(f, k) != FS_FILL) continue;
+    if (__builtin_amdgcn_ballot_w64(mask != 0u) == 0) return;   // uniform over the wave
+    for_items(mask, t.base, [&](uint32_t idx) {
         const Nbr b = nbr_of(t.L, idx);
         for_links([&](auto qc) {
             constexpr int Q = decltype(qc)::value;
@@ -500,7 +556,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
             if (cj == FS_GAS) stg<uint8_t>(F->w2, j, FS_BORN);
             else if (fj == FS_EMPTY) stg<uint8_t>(F->w2, j, FS_KEEP);
         });
-    }
+    });
 }
 
 // Pass 3.  Every cell that empties marks its liquid neighbours FS_TO_IF;
@@ -513,29 +569,33 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
     using R = typename Codec<S>::R;
     [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsTile t = fs_tile(a);
-    if (t.base >= t.ncell) return;
     const LatDev *__restrict__ L = t.L;
     const FsDev *__restrict__ F = t.F;
     const int dst = (t.flags & 1) ^ 1;
-    const bool mom = (t.flags & 2) != 0;
     if (t.base == 0) stg<uint32_t>(F->hcount[dst ^ 1], 0, 0u);   // the list unlisted by the last pass
-    const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
-    if (!any_byte(f) && !any_byte(m2)) return;
-    for (int k = 0; k < FS_CPT; ++k) {
-        const uint32_t idx = t.base + k;
-        if (idx >= t.ncell) break;
-        const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
+    uint32_t mask = 0;
+    if (t.base < t.ncell) {
+        const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
+        if (any_byte(f) || any_byte(m2))
+            for (int k = 0; k < FS_CPT; ++k) {
+                const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
+                if (t.base + k < t.ncell && (empties(w1, w2) || (w2 & FS_BORN))) mask |= 1u << k;
+            }
+    }
+    if (__builtin_amdgcn_ballot_w64(mask != 0u) == 0) return;   // uniform over the wave
+    for_items(mask, t.base, [&](uint32_t idx) {
+        // neither byte of a cell that empties or is born is written in this pass
+        const int w1 = ldg<uint8_t>(F->w1, idx), w2 = ldg<uint8_t>(F->w2, idx);
+        const Nbr b = nbr_of(L, idx);
         if (empties(w1, w2)) {
-            const Nbr b = nbr_of(L, idx);
             for_links([&](auto qc) {
                 constexpr int Q = decltype(qc)::value;
                 const uint32_t j = shifted<Q, 1>(b);
                 if (ldg<uint8_t>(F->cls, j) == FS_LIQ) stg<uint8_t>(F->w2, j, FS_TO_IF);
             });
-        } else if (w2 & FS_BORN) {
-            // a gas cell has no liquid neighbour: the qualifying neighbours are
-            // interface cells, whose rho and V' pass 1 stored
-            const Nbr b = nbr_of(L, idx);
+        } else {
+            // born: a gas cell has no liquid neighbour, so the qualifying
+            // neighbours are interface cells, whose rho and V' pass 1 stored
             double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
             int n = 0;
             for_links([&](auto qc) {
@@ -561,7 +621,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
             stg<double>(F->rho, idx, ra);
             for (int c = 0; c < 3; ++c) stp<double>(F->u, t.ncell, c, idx, ua[c]);
         }
-    }
+    });
 }
 
 // does the neighbour j convert (fill, or empty after all)?
@@ -577,16 +637,21 @@ __device__ inline bool converts(const FsDev *F, uint32_t j)
 __global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
 {
     const FsTile t = fs_tile(a);
-    if (t.base >= t.ncell) return;
     const FsDev *__restrict__ F = t.F;
-    const u32x4 f = ld16(F->w1, t.base);
-    if (!any_byte(f)) return;
-    const u32x4 m2 = ld16(F->w2, t.base);
-    for (int k = 0; k < FS_CPT; ++k) {
-        const uint32_t idx = t.base + k;
-        if (idx >= t.ncell) break;
-        const int w1 = byte_of(f, k);
-        if (!(w1 == FS_FILL || empties(w1, byte_of(m2, k)))) continue;
+    uint32_t mask = 0;
+    if (t.base < t.ncell) {
+        const u32x4 f = ld16(F->w1, t.base);
+        if (any_byte(f)) {
+            const u32x4 m2 = ld16(F->w2, t.base);
+            for (int k = 0; k < FS_CPT; ++k) {
+                const int w1 = byte_of(f, k);
+                if (t.base + k < t.ncell && (w1 == FS_FILL || empties(w1, byte_of(m2, k)))) mask |= 1u << k;
+            }
+        }
+    }
+    if (__builtin_amdgcn_ballot_w64(mask != 0u) == 0) return;   // uniform over the wave
+    for_items(mask, t.base, [&](uint32_t idx) {
+        const int w1 = ldg<uint8_t>(F->w1, idx);
         const Nbr b = nbr_of(t.L, idx);
         int n = 0;
         for_links([&](auto qc) {
@@ -610,7 +675,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
                 if ((cj == FS_IF && !converts(F, j)) || (mj & (FS_BORN | FS_TO_IF)))
                     stg<uint8_t>(F->w2, j, (uint8_t)(mj | FS_RECV));
             });
-    }
+    });
 }
 
 // Pass 5.  New classes of the converted and marked cells; the final mass and
@@ -643,57 +708,59 @@ __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
     // liquid or interface after this step (it was, or was born), or one
     // flagged in this step (pass 1 clears its flag)
     bool keep = false;
+    uint32_t mask = 0;
     if (t.base < t.ncell) {
         const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base), c0 = ld16(F->cls, t.base);
         keep = any_byte(f) || any_live(c0) || ((m2.x | m2.y | m2.z | m2.w) & 0x01010101u * FS_BORN) != 0u;
-        if (any_byte(f) || any_byte(m2)) {
-            for (int k = 0; k < FS_CPT; ++k) {
-                const uint32_t idx = t.base + k;
-                if (idx >= t.ncell) break;
-                const int w1 = byte_of(f, k), w2 = byte_of(m2, k);
-                if (!w1 && !w2) continue;
-                if (w1 == FS_FILL) {
-                    stg<uint8_t>(F->cls, idx, FS_LIQ);
-                    continue;
-                }
-                if (empties(w1, w2)) {
-                    stg<uint8_t>(F->cls, idx, FS_GAS);
-                    continue;
-                }
-                if (!(w2 & (FS_BORN | FS_TO_IF | FS_RECV))) continue;   // kept, no share
-                double m, r;
-                if (w2 & FS_BORN) {
-                    m = 0.0;
-                    r = ldg<double>(F->rho, idx);
-                } else if (w2 & FS_TO_IF) {     // a liquid cell: m = its density
-                    R o[NQ];
-                    load_cell<S>(L->f[dst], L->fm[dst], L->pstride, idx, o);
-                    R dr = 0;
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) dr += o[q];
-                    r = 1.0 + double(dr);
-                    m = r;
-                } else {
-                    m = ldg<double>(F->mass, idx);
-                    r = ldg<double>(F->rho, idx);
-                }
-                if (w2 & FS_RECV) {
-                    const Nbr b = nbr_of(L, idx);
-                    for_links([&](auto qc) {
-                        constexpr int Q = decltype(qc)::value;
-                        const uint32_t j = shifted<Q, 1>(b);
-                        if (converts(F, j)) m += ldg<double>(F->share, j);
-                    });
-                }
-                stg<double>(F->mass, idx, m);
-                stg<double>(F->lam[dst], idx, m / r);
-                if (w2 & (FS_BORN | FS_TO_IF)) {
-                    stg<uint8_t>(F->cls, idx, FS_IF);
-                    stg<uint8_t>(F->w2, idx, 0);
-                    fs_list_row(F, dst, idx / BLOCK, (t.ncell + BLOCK - 1) / BLOCK);
-                }
+        if (any_byte(f) || any_byte(m2))
+            for (int k = 0; k < FS_CPT; ++k)
+                if (t.base + k < t.ncell && (byte_of(f, k) || byte_of(m2, k))) mask |= 1u << k;
+    }
+    if (__builtin_amdgcn_ballot_w64(mask != 0u) != 0) {
+        for_items(mask, t.base, [&](uint32_t idx) {
+            // a worked cell's own bytes are written in this pass only by itself
+            const int w1 = ldg<uint8_t>(F->w1, idx), w2 = ldg<uint8_t>(F->w2, idx);
+            if (w1 == FS_FILL) {
+                stg<uint8_t>(F->cls, idx, FS_LIQ);
+                return;
             }
-        }
+            if (empties(w1, w2)) {
+                stg<uint8_t>(F->cls, idx, FS_GAS);
+                return;
+            }
+            if (!(w2 & (FS_BORN | FS_TO_IF | FS_RECV))) return;   // kept, no share
+            double m, r;
+            if (w2 & FS_BORN) {
+                m = 0.0;
+                r = ldg<double>(F->rho, idx);
+            } else if (w2 & FS_TO_IF) {     // a liquid cell: m = its density
+                R o[NQ];
+                load_cell<S>(L->f[dst], L->fm[dst], L->pstride, idx, o);
+                R dr = 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) dr += o[q];
+                r = 1.0 + double(dr);
+                m = r;
+            } else {
+                m = ldg<double>(F->mass, idx);
+                r = ldg<double>(F->rho, idx);
+            }
+            if (w2 & FS_RECV) {
+                const Nbr b = nbr_of(L, idx);
+                for_links([&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    const uint32_t j = shifted<Q, 1>(b);
+                    if (converts(F, j)) m += ldg<double>(F->share, j);
+                });
+            }
+            stg<double>(F->mass, idx, m);
+            stg<double>(F->lam[dst], idx, m / r);
+            if (w2 & (FS_BORN | FS_TO_IF)) {
+                stg<uint8_t>(F->cls, idx, FS_IF);
+                stg<uint8_t>(F->w2, idx, 0);
+                fs_list_row(F, dst, idx / BLOCK, (t.ncell + BLOCK - 1) / BLOCK);
+            }
+        });
     }
     // one flag per row of BLOCK cells: the BLOCK / FS_CPT consecutive lanes
     // that cover the row vote, the first of them writes it
