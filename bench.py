@@ -135,6 +135,9 @@ def precision_leg(n=512, steps=2000, timed=200, compare=True):
     log(f"bench: generating the {n}^3 medium")
     p = medium_parallel(n)
     ncell = n ** 3
+    # release the blocks earlier legs left in torch's cache: each lattice of
+    # this leg (up to 45 GB) then gets fresh device memory
+    torch.cuda.empty_cache()
     res = {"grid": [n, n, n], "timed_steps": timed, "warmup": 20}
     if compare:
         res["steps"] = steps
@@ -509,15 +512,15 @@ def main():
         out["wood"] = wood_leg(n, min(args.steps, 300), args.warmup)
     if not args.no_freesurface and args.storage == "f32":
         out["free_surface"] = freesurface_leg(n, min(args.steps, 300), args.warmup)
+    if args.precision:
+        out["precision_form"] = precision_leg()
+    elif not args.no_512 and args.storage == "f32":
+        out["precision_512"] = precision_leg(512, timed=100, compare=False)
     if not args.no_serve:
         single = {"f32": mlups} if args.storage == "f32" else {}
         if "reduced_storage" in out:
             single["bf16"] = out["reduced_storage"]["bf16"]["MLUPS"]
         out["serving"] = serving_leg(single_mlups=single)
-    if args.precision:
-        out["precision_form"] = precision_leg()
-    elif not args.no_512 and args.storage == "f32":
-        out["precision_512"] = precision_leg(512, timed=100, compare=False)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

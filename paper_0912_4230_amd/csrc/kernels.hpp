@@ -488,9 +488,10 @@ __device__ inline void store_pair(void *P, void *M, uint32_t n, uint32_t idx, co
     }
 }
 
-// Reciprocal, square root, reciprocal square root and exponential in two
-// forms: HW = false the correctly rounded division and square root and the
-// libm-accurate exp, HW = true the hardware instructions (about 1 ulp).  FP64
+// Reciprocal, division, square root, reciprocal square root and exponential
+// in two forms: HW = false the correctly rounded division and square root and
+// the libm-accurate exp, HW = true the hardware instructions (about 1 ulp; a
+// quotient as a product with the hardware reciprocal).  FP64
 // is always the accurate form.  HwMath<S>: FP32 storage computes with the
 // accurate forms (free there: the FP32 steps are bound by HBM, 0.945 ms either
 // way at 256^3); the 16-bit storage forms, whose rounding of the stored
@@ -508,6 +509,15 @@ __device__ inline float rcp(float x)
 }
 template <bool HW>
 __device__ inline double rcp(double x) { return 1.0 / x; }
+// a / b: the correctly rounded quotient, or (HW) a times the hardware reciprocal
+template <bool HW>
+__device__ inline float fdiv(float a, float b)
+{
+    if constexpr (HW) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+template <bool HW>
+__device__ inline double fdiv(double a, double b) { return a / b; }
 template <bool HW>
 __device__ inline float fsqrt(float x)
 {
@@ -602,10 +612,10 @@ __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], con
                 R2 += t * t;
                 dR += t * t * mu[a] * id;
             }
-            const R Rn = sqrt(R2);
+            const R Rn = fsqrt<HW>(R2);
             const R phi = s - Rn;
-            const R dphi = R(1) + (Rn > R(0) ? dR / Rn : R(0));
-            const R ds = phi / dphi;
+            const R dphi = R(1) + (Rn > R(0) ? fdiv<HW>(dR, Rn) : R(0));
+            const R ds = fdiv<HW>(phi, dphi);
             s = s - ds;
             s = s > R(0) ? s : R(0);
             if (!(fabs(ds) > Newton<R>::tol * s)) break;
@@ -1033,7 +1043,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
                 x_ie = ie;
                 for (int c = 0; c < 3; ++c) x_u[c] = u[c];
             }
-            const R omd = R(1) / R(L->tau_d);
+            const R omd = fdiv<HW>(R(1), R(L->tau_d));
             const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
             collide_h<R>(hq, R(1) - omd, H, vs);
         } else if constexpr (PHYS == PH_IMMISCIBLE) {
@@ -1110,7 +1120,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
                 for (int q = 0; q < NQ; ++q) sh += hk[q];
                 const R kk = R(3) * R(X->D[k]) * x_ie;
                 const R vs[3] = {x_u[0] + kk * x_g[0], x_u[1] + kk * x_g[1], x_u[2] + kk * x_g[2]};
-                const R omd = R(1) / R(X->tau_d[k]);
+                const R omd = fdiv<HW>(R(1), R(X->tau_d[k]));
                 const R H[3] = {omd * weight<R>(0) * sh, omd * weight<R>(1) * sh, omd * weight<R>(7) * sh};
                 collide_h<R>(hk, R(1) - omd, H, vs);
                 if (mom) stp<R>(L->mom, ncell, 5 + k, idx, sh * x_ie);
