@@ -163,6 +163,7 @@ def precision_leg(n=512, steps=2000, timed=200, compare=True):
         entry = {"ms_per_step": round(ms, 4), "MLUPS": round(ncell / ms / 1e3, 1),
                  "achieved_GBs": round(bpl * ncell / ms / 1e6, 1), "bytes_per_lup": bpl,
                  "frac_of_hbm_peak": round(bpl * ncell / ms / 1e6 / HBM_PEAK_GBS, 4),
+                 "traffic_GB_per_launch": counter_traffic(f"k_step miscible {n} {st}"),
                  "nonfinite": int(dg[7])}
         if not compare:
             if st != "f32":
@@ -299,6 +300,7 @@ def freesurface_leg(n, steps, warmup, storages=("f32", "bf16")):
         out[st] = {"ms_per_step": round(s, 5), "MLUPS_all_cells": round(ncell / s / 1e3, 1),
                    "MLUPS_live_cells": round(live / s / 1e3, 1), "live_cells": live, "interface_cells": nif,
                    "achieved_GBs_step": round(b / (s / 1e3) / 1e9, 1),
+                   "traffic_GB_per_launch_stream_collide": counter_traffic(f"k_fs_step penetration {n} {st}"),
                    "mass_drift": float(dg[4] / M0 - 1.0), "nonfinite": int(dg[7])}
         log(f"bench: free surface {st}: {out[st]}")
         sim.close()
