@@ -139,8 +139,8 @@ def test_precision_form_crop_vs_oracle(storage, crop_oracle):
     # reservoir, where the density jumps).
     bounds = {"bf16": {"rho": 5e-3, "drho": 0.5, "vel": 1.0, "conc": 0.25},
               "f16": {"rho": 5e-4, "drho": 0.05, "vel": 0.1, "conc": 1e-2},
-              "bf16s": {"rho": 3e-3, "drho": 0.3, "vel": 0.5, "conc": 5e-4},
-              "f16s": {"rho": 2e-5, "drho": 3e-3, "vel": 3e-2, "conc": 5e-4}}[storage]
+              "bf16s": {"rho": 3e-3, "drho": 0.3, "vel": 0.5, "conc": 2e-4},
+              "f16s": {"rho": 1e-5, "drho": 1e-3, "vel": 1.6e-2, "conc": 2e-4}}[storage]
     for k, b in bounds.items():
         assert e[k] < b, (k, e[k])
     f = out["f32"]
