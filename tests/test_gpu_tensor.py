@@ -136,3 +136,45 @@ def test_non_psd_tensor_rejected():
     m.kinv = k.data_ptr()
     assert B.lib().lbm_set_medium(h, C.byref(m)) == B.LBM_OK
     B.lbm_destroy(h)
+
+
+def test_rejected_medium_leaves_the_lattice_as_it_was():
+    """A set-medium call rejected on the host (an out-of-range uniform
+    porosity; an obstacle mask on a lattice without one) returns LBM_EINVAL
+    and leaves a ready full-tensor lattice as it was: it steps on bitwise like
+    a twin that never saw the call.  A medium rejected on the device (a tensor
+    that is not positive semi-definite in one cell) leaves the lattice not
+    ready: lbm_step returns LBM_ESTATE instead of stepping a half-set medium."""
+    import torch
+    from paper_0912_4230_amd import binding as B
+    from paper_0912_4230_amd.sim import Simulation
+    p = I.miscible(shape=(21, 19, 17), seed=4, ring_angle=45.0)
+    a = Simulation(p, storage="f32", uniform_medium=False)
+    b = Simulation(p, storage="f32", uniform_medium=False)
+    assert a.desc.full_tensor == 1
+    a.step(10)
+    m = B.lbm_medium()
+    m.eps_uniform = -1.0
+    m.kinv_uniform = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert B.lib().lbm_set_medium(a.h, C.byref(m)) == B.LBM_EINVAL
+    mask = torch.zeros(p.shape[::-1], dtype=torch.uint8, device="cuda")
+    m.eps_uniform = 0.5
+    m.solid = mask.data_ptr()
+    assert B.lib().lbm_set_medium(a.h, C.byref(m)) == B.LBM_EINVAL
+    a.step(10)
+    b.step(20)
+    ra, va, ca, _ = a.moments()
+    rb, vb, cb, _ = b.moments()
+    assert torch.equal(ra, rb) and torch.equal(va, vb) and torch.equal(ca, cb)
+    # a medium the device rejects: K^-1 with a large off-diagonal term in one cell
+    k = np.array(p.kinv, dtype=np.float32, copy=True)
+    k[3, 5, 6, 7] = 10.0 * float(np.max(np.abs(k[:3, 5, 6, 7]))) + 1.0
+    kt = torch.from_numpy(np.ascontiguousarray(k)).cuda()
+    et = torch.from_numpy(np.ascontiguousarray(p.eps, dtype=np.float32)).cuda()
+    m = B.lbm_medium()
+    m.eps = et.data_ptr()
+    m.kinv = kt.data_ptr()
+    assert B.lib().lbm_set_medium(a.h, C.byref(m)) == B.LBM_EINVAL
+    assert B.lib().lbm_step(a.h, 1) == B.LBM_ESTATE
+    a.close()
+    b.close()
