@@ -36,6 +36,9 @@ PLANTS = [
     ("two-fluid reservoir without its density",
      "ho[q] = cb * WGT[q] * rb;", "ho[q] = cb * WGT[q];",
      RS.test_two_fluid_reservoirs_exact_linear_colour, {}),
+    ("solute advected with V instead of the corrected V'",
+     "double D = solute_D(p), vs[3] = {Vp[0], Vp[1], Vp[2]};", "double D = solute_D(p), vs[3] = {V[0], V[1], V[2]};",
+     RS.test_solute_reservoirs_with_flow_advection_diffusion, {}),
     # hydrodynamic lattice (Sec. 2.1)
     ("no porosity on G in V' (the printed Eq. expandVsub)",
      "W[a] = V[a] + 0.5 * eps * p->G[a];\n        lam[a]", "W[a] = V[a] + 0.5 * p->G[a];\n        lam[a]",

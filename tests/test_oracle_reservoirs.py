@@ -102,3 +102,76 @@ def test_two_fluid_reservoirs_exact_linear_colour(orc):
     o.step(50)
     assert abs(o.diag()[4] / d0 - 1.0) < 1e-13
     o.close()
+
+
+def _d1q3_steady(nx, eps, tau, u, c_in, c_out):
+    """Exact steady state of the second lattice summed over the directions
+    that share c_x (the three-speed lattice of weights 1/6, 2/3, 1/6 with the
+    equilibria (eps C / 6)(1 +- 3 u) and (2/3) eps C of Eq. equild), for a
+    velocity u(x) given per fluid cell x = 1 .. nx-2, between reservoir planes
+    whose populations at rest stream in: eps C_bc / 6.  Unknowns: the
+    pre-collision sums h+(x), h-(x) and C(x); returns C(1 .. nx-2)."""
+    m = nx - 2
+    w = 1.0 / tau
+    A = np.zeros((3 * m, 3 * m))
+    b = np.zeros(3 * m)
+    P, M, Cc = 0, m, 2 * m          # offsets of h+, h-, C
+    r = 0
+    A[r, P + 0] = 1.0
+    b[r] = eps * c_in / 6.0
+    r += 1
+    for i in range(1, m):           # h+(x) = (1 - w) h+(x-1) + w e+(x-1)
+        A[r, P + i] = 1.0
+        A[r, P + i - 1] = -(1.0 - w)
+        A[r, Cc + i - 1] = -w * eps / 6.0 * (1.0 + 3.0 * u[i - 1])
+        r += 1
+    A[r, M + m - 1] = 1.0
+    b[r] = eps * c_out / 6.0
+    r += 1
+    for i in range(0, m - 1):       # h-(x) = (1 - w) h-(x+1) + w e-(x+1)
+        A[r, M + i] = 1.0
+        A[r, M + i + 1] = -(1.0 - w)
+        A[r, Cc + i + 1] = -w * eps / 6.0 * (1.0 - 3.0 * u[i + 1])
+        r += 1
+    for i in range(m):              # h+ + h- = eps C / 3 (h0 = e0 = (2/3) eps C)
+        A[r, P + i] = 1.0
+        A[r, M + i] = 1.0
+        A[r, Cc + i] = -eps / 3.0
+        r += 1
+    return np.linalg.solve(A, b)[Cc:]
+
+
+def test_solute_reservoirs_with_flow_advection_diffusion(orc):
+    """Miscible mode with rho_in > rho_out: Darcy flow from the inlet to the
+    outlet reservoir carries the solute.  For fields uniform in y and z the
+    solute update of Eqs. equild / boltzeqD summed over the directions with
+    the same c_x is exactly a three-speed advection-diffusion lattice; its
+    steady state, solved directly with the velocity V'_x(x) the oracle
+    reports (for uniform u it is C = A + B ((2D + u)/(2D - u))^x), must equal
+    the oracle's concentration.  The flow makes the profile far from the
+    linear one of pure diffusion, and the reservoir planes enter only as
+    populations at rest, w eps C_bc."""
+    nx, ny, nz = 22, 2, 1
+    tau, eps = 0.6, 0.5
+    faces = [I.Face() for _ in range(6)]
+    faces[0] = I.Face(kind=I.RESERVOIR, rho=1.05, conc=1.0)
+    faces[1] = I.Face(kind=I.RESERVOIR, rho=1.0, conc=0.0)
+    p = I.Problem(shape=(nx, ny, nz), physics=I.MISCIBLE, tau_d=tau, faces=faces).fill_defaults()
+    p.eps[:] = eps
+    p.kinv[:] = 1.0
+    o = orc.Oracle(p)
+    o.step(60000)
+    r, v, c = o.moments()
+    assert np.abs(v[1:]).max() < 1e-15                  # no transverse flow
+    u = v[0, 0, 0, 1:-1]
+    assert np.abs(v[0] - v[0, :1, :1, :]).max() < 1e-16  # uniform in y, z
+    assert 3e-3 < u.min() and u.max() < 2e-2           # a Peclet number of order 0.1-0.5 per cell
+    ex = _d1q3_steady(nx, eps, tau, u, 1.0, 0.0)
+    got = c[0, 0, 1:-1]
+    assert np.abs(got - ex).max() < 1e-11, np.abs(got - ex).max()
+    lin = linear_profile(nx, 1.0, 0.0, tau)
+    assert np.abs(got - lin).max() > 0.05              # advection shapes the profile
+    # steady: the next steps change nothing
+    o.step(100)
+    assert np.abs(o.moments()[2][0, 0, 1:-1] - got).max() < 1e-13
+    o.close()
