@@ -20,6 +20,7 @@ import test_oracle_identities as ID
 import test_oracle_reservoirs as RS
 import test_oracle_species as SP
 import test_oracle_transport as TR
+import test_oracle_twofluid as TF
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
@@ -39,6 +40,13 @@ PLANTS = [
     ("solute advected with V instead of the corrected V'",
      "double D = solute_D(p), vs[3] = {Vp[0], Vp[1], Vp[2]};", "double D = solute_D(p), vs[3] = {V[0], V[1], V[2]};",
      RS.test_solute_reservoirs_with_flow_advection_diffusion, {}),
+    # two-fluid mixture viscosity (reading of the two-fluid model)
+    ("two-fluid viscosities swapped",
+     "return C * nu1 + (1.0 - C) * nu2;", "return C * nu2 + (1.0 - C) * nu1;",
+     TF.test_layered_channel_flow_mixture_viscosity, {}),
+    ("two-fluid harmonic mixture viscosity",
+     "return C * nu1 + (1.0 - C) * nu2;", "return 1.0 / (C / nu1 + (1.0 - C) / nu2);",
+     TF.test_layered_channel_flow_mixture_viscosity, {}),
     # hydrodynamic lattice (Sec. 2.1)
     ("no porosity on G in V' (the printed Eq. expandVsub)",
      "W[a] = V[a] + 0.5 * eps * p->G[a];\n        lam[a]", "W[a] = V[a] + 0.5 * p->G[a];\n        lam[a]",

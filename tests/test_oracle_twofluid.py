@@ -88,3 +88,62 @@ def test_recolouring_keeps_interface_sharp(orc):
     assert np.abs(b[10:16] - (1 - b[21:15:-1])).max() < 1e-9
     # without recolouring the two fluids mix
     assert width(profile(0.0, 2000)) > 40
+
+
+def _layered_ode(C, G, nu1, nu2):
+    """Steady unidirectional channel flow d/dz(nu du/dz) = -G (rho = 1)
+    between no-slip planes at z = 1/2 and nz - 3/2 (halfway bounce-back),
+    with nu(z) = C nu1 + (1 - C) nu2 from the colour C(z) of the fluid cells,
+    linear between cell centres: nu du/dz = -G (z - z_s), z_s fixed by
+    u = 0 on both walls.  Returns u at the fluid cell centres."""
+    nz = C.size
+    zc = np.arange(nz, dtype=np.float64)
+    z0, z1 = 0.5, nz - 1.5
+    zf = np.linspace(z0, z1, 40001)
+    nuf = np.interp(zf, zc[1:-1], C[1:-1]) * nu1 + (1.0 - np.interp(zf, zc[1:-1], C[1:-1])) * nu2
+    inv = 1.0 / nuf
+
+    def cum(y):
+        return np.concatenate([[0.0], np.cumsum(0.5 * (y[1:] + y[:-1]) * np.diff(zf))])
+
+    a, b = cum(zf * inv), cum(inv)
+    zs = a[-1] / b[-1]                  # u(z1) = -G (a - zs b) = 0
+    u = -G * (a - zs * b)
+    return np.interp(zc[1:-1], zf, u)
+
+
+def test_layered_channel_flow_mixture_viscosity(orc):
+    """Two fluids in layers between walls (fluid 1 below, fluid 2 above, walls
+    of colour 1 and 0 so that the walls add no colour gradient), driven along
+    the layers by G, viscosity ratio 6: the steady velocity profile follows
+    the continuous momentum balance with the mixture viscosity
+    nu = C nu_1 + (1 - C) nu_2 over the oracle's own colour profile to 3e-3
+    (L2; the diffuse interface is 6 cells wide), while the harmonic mixture
+    1/nu = C/nu_1 + (1 - C)/nu_2 would be 8% away: the two-fluid dynamics
+    beyond the interface statics (Laplace law, contact angle)."""
+    nz, G, tau1, tau2 = 26, 1e-6, 0.6, 1.1
+    faces = [I.Face() for _ in range(6)]
+    faces[4] = I.Face(kind=I.WALL, angle=0.0)
+    faces[5] = I.Face(kind=I.WALL, angle=180.0)
+    p = I.Problem(shape=(1, 1, nz), physics=I.IMMISCIBLE, tau1=tau1, tau2=tau2, A=0.0, beta=0.7, faces=faces,
+                  G=(G, 0.0, 0.0)).fill_defaults()
+    p.c0[: nz // 2] = 1.0
+    o = orc.Oracle(p)
+    o.step(160000)
+    r, v, c = o.moments()
+    u, C = v[0, :, 0, 0], c[:, 0, 0]
+    nu1, nu2 = (tau1 - 0.5) / 3.0, (tau2 - 0.5) / 3.0
+    assert np.abs(v[1:]).max() < 1e-18 and np.abs(r[1:-1] - 1.0).max() < 1e-13
+    # a diffuse interface of a few cells between the layers
+    w = int(((C[1:-1] > 0.05) & (C[1:-1] < 0.95)).sum())
+    assert 2 <= w <= 8, C
+    ue = _layered_ode(C, G, nu1, nu2)
+    err = np.linalg.norm(u[1:-1] - ue) / np.linalg.norm(ue)
+    assert err < 3e-3 and abs(u.max() / ue.max() - 1.0) < 5e-3, (err, u.max(), ue.max())
+    # the maximum sits in the less viscous fluid, and the harmonic mixture is far off
+    assert np.argmax(u) < nz // 2
+    nu_h = 1.0 / (C[1:-1] / nu1 + (1.0 - C[1:-1]) / nu2)
+    Ch = np.concatenate([[0.0], (nu_h - nu2) / (nu1 - nu2), [0.0]])
+    uh = _layered_ode(Ch, G, nu1, nu2)
+    assert np.linalg.norm(u[1:-1] - uh) / np.linalg.norm(uh) > 0.05
+    o.close()
