@@ -192,3 +192,27 @@ def test_conservation_periodic_gpu():
         print(f"[conservation] {storage}: mass {dm:.2e} solute {ds:.2e}", flush=True)
         assert dm < tm and ds < ts, storage
         sim.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_two_fluid_layered_channel(storage, tol):
+    """The layered two-fluid channel of the oracle's mixture-viscosity pin
+    (1 x 1 x 26, walls of colour 1 and 0, viscosity ratio 6, G along the
+    layers), 4000 steps from the sharp initial layers: rho, V' and C against
+    the oracle."""
+    nz = 26
+    faces = [I.Face() for _ in range(6)]
+    faces[4] = I.Face(kind=I.WALL, angle=0.0)
+    faces[5] = I.Face(kind=I.WALL, angle=180.0)
+    p = I.Problem(shape=(1, 1, nz), physics=I.IMMISCIBLE, tau1=0.6, tau2=1.1, A=0.0, beta=0.7, faces=faces,
+                  G=(1e-6, 0.0, 0.0)).fill_defaults()
+    p.c0[: nz // 2] = 1.0
+    g, r, mask, dg, od = run_pair(p, 4000, storage, chunks=[1500, 2500])
+    e = errors(g, r, mask)
+    report(f"layered two-fluid channel 1x1x26 x4000 {storage}", e)
+    # FP32 V' (measured 4.5e-5): the flow is still accelerating, each step
+    # adding G = 1e-6 to velocities near 1e-3, and the oracle's own arithmetic
+    # carried out in float instead of double lands at 3.1e-5 to 4.2e-5 from the
+    # FP64 oracle here, so FP32 V' is bounded at about twice that floor
+    vtol = tol if storage == "f64" else 1e-4
+    assert e["rho"] < tol and e["conc"] < tol and e["vel"] < vtol, e
