@@ -148,6 +148,44 @@ int launch_uni(void *dst, const void *src, int lg, int row, size_t pstride, size
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 
+// NS streams of one copy read and written in place (the two kinds of step
+// of an in-place streaming scheme), with the XCD row groups and uniform row
+// bases of k_streams_uni, over a periodic cube of 2^lg cells per edge
+// (2^lg >= 256).  ODD: stream k of cell x reads and writes the element of
+// cell x - v_(k mod 19) (every element is touched by exactly one thread: the
+// shift is a bijection of the periodic cube); else the element of cell x
+// itself.  The value written is the value read plus one.
+template <class T, int NS, bool ODD>
+__global__ __launch_bounds__(256) void k_streams_aa(T *__restrict__ buf, int lg, size_t pstride)
+{
+    int blk = blockIdx.x;
+    blk = ((blk >> 3) / 4) * 32 + (blk & 7) * 4 + ((blk >> 3) % 4);
+    const int m = (1 << lg) - 1;
+    const int bpr = 1 << (lg - 8);
+    const int row = blk / bpr;
+    const int y = row & m, z = row >> lg;
+    const uint32_t x = uint32_t((blk % bpr) * 256 + threadIdx.x);
+    T v[NS];
+    uint32_t off[NS];
+    T *base[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        int ys = y, zs = z;
+        uint32_t xs = x;
+        if constexpr (ODD) {
+            ys = (y - c_probe_v[k % 19][1]) & m;
+            zs = (z - c_probe_v[k % 19][2]) & m;
+            xs = (x - uint32_t(c_probe_v[k % 19][0])) & uint32_t(m);
+        }
+        base[k] = buf + k * pstride + (((size_t(zs) << lg) + size_t(ys)) << lg);
+        off[k] = xs * uint32_t(sizeof(T));
+        v[k] = __builtin_nontemporal_load(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base[k]) + off[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        __builtin_nontemporal_store(T(v[k] + T(1)), reinterpret_cast<T *>(reinterpret_cast<char *>(base[k]) + off[k]));
+}
+
 template <class T, bool XG>
 void launch_shift_xg(T *d, const T *r, int lg, int row, int shift, size_t pstride, size_t pitch, dim3 grid,
                      hipStream_t s)
@@ -240,6 +278,25 @@ int probe_streams_uni(void *dst, const void *src, int lg, int ns, int row, size_
     if (ns == 38 && elem == 4) return launch_uni<uint32_t, 38>(dst, src, lg, row, pstride, pitch, s);
     if (ns == 38 && elem == 2) return launch_uni<uint16_t, 38>(dst, src, lg, row, pstride, pitch, s);
     return 1;
+}
+
+// k_streams_aa: ns = 38 or 19 streams of 4-byte elements read and written in
+// place in one plane-major copy (ns * pstride elements, pstride >= 2^(3 lg)),
+// odd = 1 shifted, 0 local, over a cube of 2^lg cells per edge (8 <= lg <= 9).
+// Returns 0, or 1 on a rejected argument, 2 on a launch error.  Asynchronous.
+int probe_streams_aa(void *buf, int lg, int ns, int odd, size_t pstride, void *stream)
+{
+    if (!buf || lg < 8 || lg > 9 || (ns != 38 && ns != 19)) return 1;
+    const size_t n = size_t(1) << (3 * lg);
+    if (pstride < n) return 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid(unsigned(n / 256)), block(256);
+    uint32_t *b = static_cast<uint32_t *>(buf);
+    if (ns == 38 && odd) hipLaunchKernelGGL((k_streams_aa<uint32_t, 38, true>), grid, block, 0, s, b, lg, pstride);
+    else if (ns == 38) hipLaunchKernelGGL((k_streams_aa<uint32_t, 38, false>), grid, block, 0, s, b, lg, pstride);
+    else if (odd) hipLaunchKernelGGL((k_streams_aa<uint32_t, 19, true>), grid, block, 0, s, b, lg, pstride);
+    else hipLaunchKernelGGL((k_streams_aa<uint32_t, 19, false>), grid, block, 0, s, b, lg, pstride);
+    return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 
 // Copy `bytes` (a multiple of 16; both pointers 16-byte aligned device

@@ -126,6 +126,11 @@ def run_streams(args):
     probe.probe_streams38_cube.restype = ctypes.c_int
     probe.probe_streams38_cube.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
+    probe.probe_streams_aa.restype = ctypes.c_int
+    probe.probe_streams_aa.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                       ctypes.c_void_p]
+    if args.inplace:
+        return run_inplace(args, probe)
     probe.probe_streams_uni.restype = ctypes.c_int
     probe.probe_streams_uni.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_size_t, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
@@ -182,6 +187,41 @@ def run_streams(args):
           f"{2 * 38 * args.elem * n / ms / 1e6:.1f} GB/s (HIP events)", flush=True)
 
 
+def run_inplace(args, probe):
+    """The in-place probe: 38 (or with --pairs 19) planes of 4-byte elements of
+    one plane-major copy, every element read and written back by one thread,
+    at the cell's own place (even) or its link's upstream cell (odd), with the
+    XCD row groups of the lattice step."""
+    import torch
+    lg = args.size.bit_length() - 1
+    if args.size != 1 << lg or args.size < 256 or args.elem != 4 or args.layout != "plane":
+        raise SystemExit("streams --inplace: size 256 or 512, 4-byte elements, plane layout")
+    n = args.size ** 3
+    ns = 19 if args.pairs else 38
+    pstride = n + args.pad
+    a = torch.zeros(ns * pstride, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    odd = int(args.inplace == "odd")
+
+    def launch():
+        rc = probe.probe_streams_aa(a.data_ptr(), lg, ns, odd, pstride, stream.cuda_stream)
+        if rc:
+            raise SystemExit(f"probe_streams_aa failed ({rc})")
+    launch()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.reps):
+        launch()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.reps
+    print(f"profile_run streams: in place ({args.inplace}), {args.size}^3 cells, {ns} planes of 4-byte elements, "
+          f"pad {args.pad} elements: {ms:.3f} ms per launch, {2 * ns * 4 * n / ms / 1e6:.1f} GB/s (HIP events)",
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -204,6 +244,8 @@ def main():
                    help="19 planes of elements twice --elem wide (both lattices' values of a link side by side)")
     t.add_argument("--uniform", action="store_true",
                    help="shifted pull with XCD row groups and uniform row bases (size >= 256)")
+    t.add_argument("--inplace", choices=["odd", "even"],
+                   help="one copy read and written in place: at the link's upstream cell (odd) or the cell (even)")
     t.add_argument("--pad", type=int, default=128, help="elements of padding after each plane (slice)")
     t.add_argument("--elem", type=int, default=4, choices=[4, 2], help="element bytes")
     t.add_argument("--reps", type=int, default=10)
