@@ -127,11 +127,13 @@ template <> struct Codec<f16_t> {
     }
 };
 
-// Split 16-bit codecs: population q of a cell is w_q m + r_q, where m (the
-// cell's population sum, i.e. drho for the hydrodynamic lattice and eps C or
-// rho_1 for the second one) is kept in an FP32 plane and only the remainder
-// r_q -- the velocity and non-equilibrium part, orders of magnitude below
-// w_q m in low-Mach porous flow -- is rounded to 16 bits.
+// Split 16-bit codecs: population q of a cell is w_q m + r_q, where m (about
+// the cell's population sum, i.e. drho for the hydrodynamic lattice and eps C
+// or rho_1 for the second one) is kept in an FP32 plane and only the
+// remainder r_q -- the velocity and non-equilibrium part, orders of magnitude
+// below w_q m in low-Mach porous flow -- is rounded to 16 bits.  The stored m
+// absorbs the rounding of the remainders, so that the decoded populations sum
+// to the cell's population sum (store_all in kernels.hpp).
 struct bf16s_t { uint16_t v; };
 struct f16s_t { uint16_t v; };
 
@@ -147,6 +149,10 @@ template <> struct Codec<bf16s_t> {
         return float(__builtin_bit_cast(__bf16, ld(reinterpret_cast<const GL uint16_t *>(p))));
     }
     __device__ static void store(GL bf16s_t *p, R v) { Codec<bf16_t>::store(reinterpret_cast<GL bf16_t *>(p), v); }
+    // the 16-bit word of v (rounded to nearest even) and its value
+    __device__ static uint16_t enc(R v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+    __device__ static R dec(uint16_t b) { return float(__builtin_bit_cast(__bf16, b)); }
+    __device__ static void store_bits(GL bf16s_t *p, uint16_t b) { st(reinterpret_cast<GL uint16_t *>(p), b); }
 };
 
 template <> struct Codec<f16s_t> {
@@ -157,6 +163,9 @@ template <> struct Codec<f16s_t> {
         return Codec<f16_t>::load(reinterpret_cast<const GL f16_t *>(p));
     }
     __device__ static void store(GL f16s_t *p, R v) { Codec<f16_t>::store(reinterpret_cast<GL f16_t *>(p), v); }
+    __device__ static uint16_t enc(R v) { return __builtin_bit_cast(uint16_t, _Float16(v)); }
+    __device__ static R dec(uint16_t b) { return float(__builtin_bit_cast(_Float16, b)); }
+    __device__ static void store_bits(GL f16s_t *p, uint16_t b) { st(reinterpret_cast<GL uint16_t *>(p), b); }
 };
 
 // Paired 16-bit storage: the value of a link in both lattices of the
@@ -175,33 +184,36 @@ template <class S> struct PairCodec;
 template <> struct PairCodec<bf16_t> {
     using W = uint32_t;
     using R = float;
-    __device__ static void load(const GL W *p, R &a, R &b)
+    __device__ static void decode(W w, R &a, R &b)
     {
-        const uint32_t w = ld(p);
         a = __uint_as_float(w << 16);
         b = __uint_as_float(w & 0xffff0000u);
     }
-    __device__ static void store(GL W *p, R a, R b)
+    __device__ static W encode(R a, R b)
     {
         const bf16x2_t v = {(__bf16)a, (__bf16)b};
-        st(p, __builtin_bit_cast(uint32_t, v));
+        return __builtin_bit_cast(uint32_t, v);
     }
+    __device__ static void load(const GL W *p, R &a, R &b) { decode(ld(p), a, b); }
+    __device__ static void store(GL W *p, R a, R b) { st(p, encode(a, b)); }
 };
 
 template <> struct PairCodec<f16_t> {
     using W = uint32_t;
     using R = float;
-    __device__ static void load(const GL W *p, R &a, R &b)
+    __device__ static void decode(W w, R &a, R &b)
     {
-        const f16x2_t v = __builtin_bit_cast(f16x2_t, ld(p));
+        const f16x2_t v = __builtin_bit_cast(f16x2_t, w);
         a = float(v.x);
         b = float(v.y);
     }
-    __device__ static void store(GL W *p, R a, R b)
+    __device__ static W encode(R a, R b)
     {
         const f16x2_t v = {_Float16(a), _Float16(b)};
-        st(p, __builtin_bit_cast(uint32_t, v));
+        return __builtin_bit_cast(uint32_t, v);
     }
+    __device__ static void load(const GL W *p, R &a, R &b) { decode(ld(p), a, b); }
+    __device__ static void store(GL W *p, R a, R b) { st(p, encode(a, b)); }
 };
 
 // the split codecs pair their 16-bit remainders the same way (and their two

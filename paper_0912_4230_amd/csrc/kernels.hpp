@@ -399,8 +399,15 @@ __device__ inline void store_each(void *P, uint32_t n, uint32_t idx, const typen
     if constexpr (Q + 1 < NQ) store_each<S, Q + 1>(P, n, idx, v);
 }
 
-// Store the 19 populations of a cell (split codecs: m = sum_q v_q in FP32 and
-// the remainders v_q - w_q m in 16 bits).
+// Store the 19 populations of a cell.  Split codecs: with m = sum_q v_q in
+// FP32, the remainders r_q = v_q - w_q m are rounded to 16 bits (r~_q) and
+// the mass plane holds m - sum_q r~_q, so that the decoded populations
+// w_q (m - sum r~) + r~_q sum to m again (the weights sum to 1): the cell's
+// mass survives the rounding.  Storing m itself lost mass steadily: in
+// opposite links the remainders are +-a + b, and where b is below the 16-bit
+// resolution of a the two roundings drop about 2b with one sign.  The
+// correction moves every decoded population by w_q times the rounding sum
+// and leaves the momentum as it was (sum_q w_q v_q = 0).
 template <class S>
 __device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, const typename Codec<S>::R *v)
 {
@@ -409,11 +416,14 @@ __device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, con
         R m = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) m += v[q];
-        R r[NQ];
+        R s = 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) r[q] = fma(-weight<R>(q), m, v[q]);
-        stg<R>(M, idx, m);
-        store_each<S>(P, n, idx, r);
+        for (int q = 0; q < NQ; ++q) {
+            const uint16_t e = Codec<S>::enc(fma(-weight<R>(q), m, v[q]));
+            s += Codec<S>::dec(e);
+            Codec<S>::store_bits(at(plane_w<S>(P, n, q), idx), e);
+        }
+        stg<R>(M, idx, m - s);
     } else {
         store_each<S>(P, n, idx, v);
     }
@@ -463,7 +473,8 @@ __device__ inline void pull_pair(const void *P, const void *M, uint32_t n, uint3
 }
 
 // Store of both lattices' 19 populations into paired planes (split codecs:
-// the masses as in store_all, one pair per cell).
+// the masses as in store_all, less the sums of the rounded remainders, one
+// pair per cell).
 template <class S>
 __device__ inline void store_pair(void *P, void *M, uint32_t n, uint32_t idx, const typename Codec<S>::R *a,
                                   const typename Codec<S>::R *c)
@@ -477,11 +488,17 @@ __device__ inline void store_pair(void *P, void *M, uint32_t n, uint32_t idx, co
             ma += a[q];
             mc += c[q];
         }
-        stg<f32x2_t>(M, idx, f32x2_t{ma, mc});
+        R sa = 0, sc = 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            PairCodec<S>::store(at(plane_w<W>(P, n, q), idx), fma(-weight<R>(q), ma, a[q]),
-                                fma(-weight<R>(q), mc, c[q]));
+        for (int q = 0; q < NQ; ++q) {
+            const W wd = PairCodec<S>::encode(fma(-weight<R>(q), ma, a[q]), fma(-weight<R>(q), mc, c[q]));
+            R ta, tc;
+            PairCodec<S>::decode(wd, ta, tc);
+            sa += ta;
+            sc += tc;
+            st(at(plane_w<W>(P, n, q), idx), wd);
+        }
+        stg<f32x2_t>(M, idx, f32x2_t{ma - sa, mc - sc});
     } else {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) PairCodec<S>::store(at(plane_w<W>(P, n, q), idx), a[q], c[q]);

@@ -134,7 +134,8 @@ def test_split_storage_conserves_each_solute():
     sim.step(200)
     t1 = np.array(sim.solute_totals())
     print(f"[physics] f16s three solutes, closed box: mass drift {np.abs(t1 / t0 - 1).max():.2e}", flush=True)
-    # each population is w_q m + r_q with m exact to FP32 and r_q rounded to
-    # FP16: the decoded sum moves by the rounding of the remainders
-    assert np.abs(t1 / t0 - 1).max() < 1e-4
+    # each population is w_q m + r_q with r_q rounded to FP16 and m in FP32,
+    # stored so that the decoded populations sum to the cell's population sum
+    # (measured drift 1.9e-6)
+    assert np.abs(t1 / t0 - 1).max() < 4e-6
     sim.close()
