@@ -314,6 +314,36 @@ lbm_status lbm_set_stream(lbm_t h, void *hip_stream);
 /* Completed steps since lbm_set_medium, or -1 for a NULL handle. */
 long long lbm_steps_done(lbm_t h);
 
+/* Checkpoint and resume (the paper runs a simulation to a steady state in one
+ * go, Sec. 4; a server that pre-empts lattices, or a long run that outlives
+ * its process, saves and restores them).  A checkpoint is opaque host bytes:
+ * a header, then every byte of the lattice's workspace (populations of both
+ * copies, masses, medium planes, diagnostics, free-surface state, further
+ * solutes) except the blocks that hold device addresses.
+ *
+ * lbm_state_bytes: the size of a checkpoint of h (about its workspace size),
+ * or 0 for a NULL handle.
+ * lbm_save_state: writes the checkpoint of h's state after the work issued on
+ * its stream into host_dst (host memory of at least `bytes` >=
+ * lbm_state_bytes(h) bytes, the caller's).  Synchronises the stream.
+ * LBM_ESTATE before lbm_set_medium, LBM_EINVAL for NULL pointers or a short
+ * buffer.
+ * lbm_load_state: replaces h's state by the checkpoint in host_src and sets
+ * its completed steps to the saved count; h must have been created from the
+ * same description (sizes, physics, storage, solutes, tensor and mask flags)
+ * and given a medium of the same form (uniform eps and K^-1 with the same
+ * values, or per-cell fields) by lbm_set_medium; its other parameters (tau,
+ * G, ...) and its workspace address may differ, and the next steps use them;
+ * with the same parameters they are bitwise the steps the saved lattice would
+ * have taken.
+ * Synchronises the stream.  LBM_ESTATE before lbm_set_medium; LBM_EINVAL for
+ * a checkpoint that does not fit h (nothing is written then); on a device
+ * error during the copy (LBM_EDEVICE) the state is partly written and h
+ * needs lbm_set_medium again (LBM_ESTATE until then). */
+size_t lbm_state_bytes(lbm_t h);
+lbm_status lbm_save_state(lbm_t h, void *host_dst, size_t bytes);
+lbm_status lbm_load_state(lbm_t h, const void *host_src, size_t bytes);
+
 /* Free the host handle (the workspace stays the caller's). */
 lbm_status lbm_destroy(lbm_t h);
 

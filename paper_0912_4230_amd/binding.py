@@ -22,7 +22,7 @@ STORAGE_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "bf16": LBM_BF16_DEV, "f16": LB
                  "bf16s": LBM_BF16_SPLIT, "f16s": LBM_F16_SPLIT}
 EXPORTED = ["lbm_workspace_bytes", "lbm_create", "lbm_create_static", "lbm_set_medium", "lbm_step", "lbm_step_batch",
             "lbm_moments", "lbm_populations", "lbm_solute_totals", "lbm_free_surface", "lbm_set_stream", "lbm_steps_done", "lbm_destroy",
-            "lbm_lattice", "lbm_strerror"]
+            "lbm_lattice", "lbm_strerror", "lbm_state_bytes", "lbm_save_state", "lbm_load_state"]
 
 
 class lbm_face(C.Structure):
@@ -104,6 +104,12 @@ def lib():
         L.lbm_free_surface.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_strerror.argtypes = [C.c_int]
+        L.lbm_state_bytes.restype = C.c_size_t
+        L.lbm_state_bytes.argtypes = [vp]
+        L.lbm_save_state.restype = C.c_int
+        L.lbm_save_state.argtypes = [vp, vp, C.c_size_t]
+        L.lbm_load_state.restype = C.c_int
+        L.lbm_load_state.argtypes = [vp, vp, C.c_size_t]
         _lib = L
     return _lib
 
@@ -184,6 +190,21 @@ def lbm_free_surface(h, cls_ptr: int = 0, mass_ptr: int = 0, lambda_ptr: int = 0
 
 def lbm_steps_done(h) -> int:
     return int(lib().lbm_steps_done(h))
+
+
+def lbm_state_bytes(h) -> int:
+    return int(lib().lbm_state_bytes(h))
+
+
+def lbm_save_state(h, buf) -> int:
+    """Write the checkpoint of h into buf (a writable numpy uint8 array of at
+    least lbm_state_bytes(h) bytes)."""
+    return _check(lib().lbm_save_state(h, C.c_void_p(buf.ctypes.data), C.c_size_t(buf.nbytes)), "lbm_save_state")
+
+
+def lbm_load_state(h, buf) -> int:
+    """Replace h's state by the checkpoint in buf (a numpy uint8 array)."""
+    return _check(lib().lbm_load_state(h, C.c_void_p(buf.ctypes.data), C.c_size_t(buf.nbytes)), "lbm_load_state")
 
 
 def lbm_destroy(h) -> int:

@@ -655,6 +655,88 @@ void setup_handle(lbm_sim *h, const lbm_desc *d, void *dev_workspace, size_t ws_
 }
 
 // ---------------------------------------------------------------------------
+// Checkpoints.  A lattice's state is its workspace (populations of both
+// copies, masses, medium planes, diagnostics, free-surface planes and lists,
+// further solutes) plus three host values: the completed steps, the copy
+// holding the current state and the medium's form (uniform or per cell).
+// Three blocks of the workspace hold absolute device pointers (the parameter
+// block at its start, the free-surface and further-solute blocks) and belong
+// to the workspace they sit in; a checkpoint is every other byte, after a
+// header that records what the layout depends on, so that it can be loaded
+// into another workspace of the same description and medium.
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version, cur;
+    int64_t steps;
+    uint64_t total, payload;
+    int32_t nx, ny, nz, physics, storage, nspecies, full_tensor, solid_mask;
+    int32_t uniform_eps, uniform_kinv, medium_tensor, pad;
+    double eps_u, kinv_u[3];
+};
+constexpr uint64_t CKPT_MAGIC = 0x54504b434d424c50ull;   // "PLBMCKPT"
+
+struct Span {
+    size_t off, len;
+};
+
+// the byte ranges of the workspace a checkpoint holds, in layout order
+int state_spans(const lbm_sim *h, Span out[3])
+{
+    const Layout &L = h->lay;
+    size_t at = L.err;
+    int n = 0;
+    if (h->host.fs) {
+        out[n++] = {at, L.fs - at};
+        at = L.fs + sizeof(FsDev);
+    }
+    if (h->host.ms) {
+        out[n++] = {at, L.ms - at};
+        at = L.ms + sizeof(MsDev);
+    }
+    out[n++] = {at, L.total - at};
+    return n;
+}
+
+CkptHeader ckpt_header(const lbm_sim *h)
+{
+    CkptHeader H;
+    memset(&H, 0, sizeof(H));
+    H.magic = CKPT_MAGIC;
+    H.version = 1;
+    H.cur = uint32_t(h->cur);
+    H.steps = h->steps;
+    H.total = h->lay.total;
+    Span sp[3];
+    const int n = state_spans(h, sp);
+    for (int k = 0; k < n; ++k) H.payload += sp[k].len;
+    H.nx = h->d.nx;
+    H.ny = h->d.ny;
+    H.nz = h->d.nz;
+    H.physics = h->d.physics;
+    H.storage = h->d.storage;
+    H.nspecies = h->d.nspecies;
+    H.full_tensor = h->d.full_tensor;
+    H.solid_mask = h->d.solid_mask;
+    H.uniform_eps = h->host.uniform_eps;
+    H.uniform_kinv = h->host.uniform_kinv;
+    H.medium_tensor = h->host.full_tensor;
+    H.eps_u = h->host.uniform_eps ? h->host.eps_u : 0.0;
+    for (int a = 0; a < 3; ++a) H.kinv_u[a] = h->host.uniform_kinv ? h->host.kinv_u[a] : 0.0;
+    return H;
+}
+
+// a checkpoint header fits a handle: same layout and the same medium form
+bool ckpt_fits(const CkptHeader &H, const CkptHeader &E)
+{
+    return H.magic == CKPT_MAGIC && H.version == E.version && H.cur <= 1 && H.steps >= 0 && H.total == E.total &&
+           H.payload == E.payload && H.nx == E.nx && H.ny == E.ny && H.nz == E.nz && H.physics == E.physics &&
+           H.storage == E.storage && H.nspecies == E.nspecies && H.full_tensor == E.full_tensor &&
+           H.solid_mask == E.solid_mask && H.uniform_eps == E.uniform_eps && H.uniform_kinv == E.uniform_kinv &&
+           H.medium_tensor == E.medium_tensor && H.eps_u == E.eps_u && H.kinv_u[0] == E.kinv_u[0] &&
+           H.kinv_u[1] == E.kinv_u[1] && H.kinv_u[2] == E.kinv_u[2];
+}
+
+// ---------------------------------------------------------------------------
 // Lattices for callers that cannot allocate (lbm_create_static): the
 // workspace is this file-scope array, one copy per GPU, placed on every
 // device the library runs on when the code object is loaded and held until
@@ -964,6 +1046,57 @@ lbm_status lbm_set_stream(lbm_t h, void *hip_stream)
 }
 
 long long lbm_steps_done(lbm_t h) { return h ? h->steps : -1; }
+
+size_t lbm_state_bytes(lbm_t h)
+{
+    return h ? size_t(sizeof(CkptHeader) + ckpt_header(h).payload) : 0;
+}
+
+lbm_status lbm_save_state(lbm_t h, void *host_dst, size_t bytes)
+{
+    if (!h || !host_dst) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    const CkptHeader H = ckpt_header(h);
+    if (bytes < sizeof(CkptHeader) + H.payload) return LBM_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    memcpy(host_dst, &H, sizeof(H));
+    char *o = static_cast<char *>(host_dst) + sizeof(H);
+    Span sp[3];
+    const int n = state_spans(h, sp);
+    lbm_status st;
+    for (int k = 0; k < n; ++k) {
+        if ((st = dev_err(hipMemcpyAsync(o, h->ws + sp[k].off, sp[k].len, hipMemcpyDeviceToHost, h->stream)))) return st;
+        o += sp[k].len;
+    }
+    return dev_err(hipStreamSynchronize(h->stream));
+}
+
+lbm_status lbm_load_state(lbm_t h, const void *host_src, size_t bytes)
+{
+    if (!h || !host_src) return LBM_EINVAL;
+    if (!h->ready) return LBM_ESTATE;
+    if (bytes < sizeof(CkptHeader)) return LBM_EINVAL;
+    CkptHeader H;
+    memcpy(&H, host_src, sizeof(H));
+    if (!ckpt_fits(H, ckpt_header(h)) || bytes < sizeof(CkptHeader) + H.payload) return LBM_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return LBM_EDEVICE;
+    // the workspace is rewritten from here on: the handle is ready again only
+    // when every copy has completed
+    h->ready = 0;
+    const char *o = static_cast<const char *>(host_src) + sizeof(H);
+    Span sp[3];
+    const int n = state_spans(h, sp);
+    lbm_status st;
+    for (int k = 0; k < n; ++k) {
+        if ((st = dev_err(hipMemcpyAsync(h->ws + sp[k].off, o, sp[k].len, hipMemcpyHostToDevice, h->stream)))) return st;
+        o += sp[k].len;
+    }
+    if ((st = dev_err(hipStreamSynchronize(h->stream)))) return st;
+    h->steps = H.steps;
+    h->cur = int(H.cur);
+    h->ready = 1;
+    return LBM_OK;
+}
 
 lbm_status lbm_destroy(lbm_t h)
 {

@@ -171,6 +171,18 @@ class Simulation:
         B.lbm_populations(self.h, lattice, out.data_ptr())
         return out
 
+    def save_state(self) -> np.ndarray:
+        """Checkpoint of the lattice (host bytes, lbm_save_state)."""
+        buf = np.empty(B.lbm_state_bytes(self.h), dtype=np.uint8)
+        B.lbm_save_state(self.h, buf)
+        return buf
+
+    def load_state(self, buf: np.ndarray) -> "Simulation":
+        """Resume from a checkpoint taken from a lattice of the same problem
+        (lbm_load_state)."""
+        B.lbm_load_state(self.h, np.ascontiguousarray(buf, dtype=np.uint8))
+        return self
+
     def solute_totals(self):
         """Miscible: Sum eps C_k over fluid cells for every solute (FP64 list)."""
         return B.lbm_solute_totals(self.h, self.problem.nspecies)
