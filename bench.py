@@ -87,11 +87,24 @@ def time_gpu(problem, storage, steps, warmup):
     return ms, dg
 
 
-def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50, single_mlups=None):
+class _StorageTag:
+    """Text sink for serve()'s JSON records that adds the storage form."""
+
+    def __init__(self, sink, storage):
+        self.sink, self.storage = sink, storage
+
+    def write(self, line):
+        rec = json.loads(line)
+        rec["storage"] = self.storage
+        self.sink.write(json.dumps(rec) + "\n")
+
+
+def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50, single_mlups=None, jsonl_path=None):
     """The serving workload: 64 requests, Poisson arrivals at 4/s, cubic edge
     log-uniform in [48, 192], 70% miscible / 30% two-fluid, 500-5000 steps,
     seeded spruce-like media (anisotropy U[10, 200]), admitted under an HBM
-    budget with lattices resident on the device (continuous batching)."""
+    budget with lattices resident on the device (continuous batching).  With
+    `jsonl_path`, one JSON record per request (its storage added) goes there."""
     from concurrent.futures import ThreadPoolExecutor
     from paper_0912_4230_amd import inputs as I
     from paper_0912_4230_amd.serve import GpuExecutor, serve
@@ -102,10 +115,12 @@ def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50, single
     out = {"requests": len(reqs), "arrival_rate_per_s": 4.0, "budget_GB": budget_gb, "tick_steps": tick_steps,
            "offered_GLUP": round(sum(r.edge ** 3 * r.steps for r in reqs) / 1e9, 2),
            "percentile_rule": "nearest rank over the 64 latencies (p99 = the largest)"}
+    sink = open(jsonl_path, "w") if jsonl_path else None
     for st in storages:
         log(f"bench: serving {st}")
         ex = GpuExecutor(storage=st, problems=probs)
-        res = serve(reqs, ex, int(budget_gb * 1e9), tick_steps=tick_steps)
+        res = serve(reqs, ex, int(budget_gb * 1e9), tick_steps=tick_steps,
+                    jsonl=_StorageTag(sink, st) if sink is not None else None)
         out[st] = {"p50_s": round(res["p50_s"], 3), "p99_s": round(res["p99_s"], 3),
                    "mean_s": round(res["mean_s"], 3), "aggregate_MLUPS": round(res["aggregate_mlups"], 1),
                    "completed": res["completed"], "failed": res["failed"], "max_active": res["max_active"],
@@ -114,6 +129,8 @@ def serving_leg(storages=("f32", "bf16"), budget_gb=200.0, tick_steps=50, single
         if single_mlups and st in single_mlups:
             out[st]["aggregate_vs_single_lattice_256"] = round(res["aggregate_mlups"] / single_mlups[st], 3)
         log(f"bench: serving {st}: {out[st]}")
+    if sink is not None:
+        sink.close()
     return out
 
 
@@ -456,6 +473,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-log", default=None, help="write one JSON record per served request to this file")
     ap.add_argument("--no-obstacles", action="store_true")
     ap.add_argument("--no-inclined", action="store_true")
     ap.add_argument("--no-freesurface", action="store_true")
@@ -551,7 +569,7 @@ def main():
         single = {"f32": mlups} if args.storage == "f32" else {}
         if "reduced_storage" in out:
             single["bf16"] = out["reduced_storage"]["bf16"]["MLUPS"]
-        out["serving"] = serving_leg(single_mlups=single)
+        out["serving"] = serving_leg(single_mlups=single, jsonl_path=args.serve_log)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

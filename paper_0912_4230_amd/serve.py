@@ -22,9 +22,10 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import json
 import math
 import time
-from typing import Callable, Dict, List, Optional
+from typing import Callable, Dict, List, Optional, TextIO
 
 from . import inputs as I
 
@@ -126,11 +127,25 @@ def nearest_rank(values: List[float], p: float) -> float:
     return v[k - 1]
 
 
+def record(o: Outcome) -> Dict:
+    """The JSON record of one request: times on the serving clock (s since the
+    loop started), latency, size, status and the request's own rate while it
+    was resident (cell updates / (completed - admitted), MLUPS; null when it
+    never ran)."""
+    resident = o.completed - o.admitted
+    ran = o.status in ("ok", "unstable") and resident > 0
+    return {"rid": o.rid, "arrival_s": round(o.arrival, 6), "admitted_s": round(o.admitted, 6),
+            "completed_s": round(o.completed, 6), "latency_s": round(o.latency, 6), "cells": o.cells,
+            "steps": o.steps, "status": o.status,
+            "mlups_resident": round(o.cells * o.steps / resident / 1e6, 3) if ran else None}
+
+
 def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: int = 50,
           clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-          log: Optional[Callable[[str], None]] = None) -> Dict:
+          log: Optional[Callable[[str], None]] = None, jsonl: Optional[TextIO] = None) -> Dict:
     """Run the request stream to completion; returns per-request outcomes and
-    aggregate statistics."""
+    aggregate statistics.  With `jsonl` (a text stream) every request's
+    record() is written as one JSON line as soon as its outcome is known."""
     pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
     active: List[Job] = []
     used = 0
@@ -142,6 +157,11 @@ def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: in
     def now():
         return clock() - t0
 
+    def settle(o: Outcome):
+        outcomes[o.rid] = o
+        if jsonl is not None:
+            jsonl.write(json.dumps(record(o)) + "\n")
+
     def admit_ready():
         nonlocal used
         while pending and pending[0].arrival <= now():
@@ -150,13 +170,13 @@ def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: in
                 nb = executor.workspace_bytes(req)
             except Exception as e:  # invalid request description
                 pending.popleft()
-                outcomes[req.rid] = Outcome(req.rid, req.arrival, now(), now(), now() - req.arrival,
-                                            req.edge ** 3, req.steps, f"error: {e}")
+                settle(Outcome(req.rid, req.arrival, now(), now(), now() - req.arrival,
+                               req.edge ** 3, req.steps, f"error: {e}"))
                 continue
             if nb <= 0 or nb > budget_bytes:
                 pending.popleft()
-                outcomes[req.rid] = Outcome(req.rid, req.arrival, now(), now(), now() - req.arrival,
-                                            req.edge ** 3, req.steps, "rejected")
+                settle(Outcome(req.rid, req.arrival, now(), now(), now() - req.arrival,
+                               req.edge ** 3, req.steps, "rejected"))
                 continue
             if used + nb > budget_bytes:
                 break          # FIFO: wait for memory to free up
@@ -164,8 +184,8 @@ def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: in
             try:
                 h = executor.admit(req)
             except Exception as e:
-                outcomes[req.rid] = Outcome(req.rid, req.arrival, now(), now(), now() - req.arrival,
-                                            req.edge ** 3, req.steps, f"error: {e}")
+                settle(Outcome(req.rid, req.arrival, now(), now(), now() - req.arrival,
+                               req.edge ** 3, req.steps, f"error: {e}"))
                 continue
             used += nb
             active.append(Job(req, h, nb, req.steps, now()))
@@ -175,8 +195,8 @@ def serve(requests: List[I.Request], executor, budget_bytes: int, tick_steps: in
         for j in jobs:
             status, res = executor.finish(j.handle)
             t = now()
-            outcomes[j.req.rid] = Outcome(j.req.rid, j.req.arrival, j.admitted, t, t - j.req.arrival,
-                                          j.req.edge ** 3, j.req.steps, status, res)
+            settle(Outcome(j.req.rid, j.req.arrival, j.admitted, t, t - j.req.arrival,
+                           j.req.edge ** 3, j.req.steps, status, res))
             executor.release(j.handle)
             used -= j.nbytes
             if log:

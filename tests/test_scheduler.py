@@ -155,6 +155,36 @@ def test_next_tick_issued_before_waiting():
     assert abs(st["busy_s"] - ex.busy) < 1e-12
 
 
+def test_jsonl_records_every_request():
+    """One JSON line per request as its outcome is known: the statuses and
+    times of the returned outcomes, latency = completion - arrival, and a
+    resident rate for the requests that ran."""
+    import io
+    import json
+    clk = Clock()
+    reqs = _reqs(12)
+    big = max(reqs, key=lambda r: r.edge)
+    ex = MockExecutor(clk, rate=1e8, unstable={reqs[2].rid})
+    out = io.StringIO()
+    st = serve(reqs, ex, 100 * big.edge ** 3 - 1, tick_steps=50, clock=clk, sleep=clk.sleep, jsonl=out)
+    lines = [json.loads(x) for x in out.getvalue().splitlines()]
+    assert sorted(r["rid"] for r in lines) == sorted(r.rid for r in reqs)
+    for r in lines:
+        o = st["outcomes"][r["rid"]]
+        assert r["status"] == o.status
+        assert abs(r["latency_s"] - (r["completed_s"] - r["arrival_s"])) < 1e-5
+        assert r["admitted_s"] >= r["arrival_s"] - 1e-9 and r["completed_s"] >= r["admitted_s"]
+        if o.status in ("ok", "unstable"):
+            assert r["mlups_resident"] > 0
+            assert abs(r["mlups_resident"] - o.cells * o.steps / (o.completed - o.admitted) / 1e6) < 1e-3
+        else:
+            assert r["mlups_resident"] is None
+    assert {r["status"] for r in lines} >= {"ok", "unstable", "rejected"}
+    # records appear in completion order
+    done = [r["completed_s"] for r in lines]
+    assert done == sorted(done)
+
+
 def test_nearest_rank():
     v = list(range(1, 65))
     assert nearest_rank(v, 50) == 32
