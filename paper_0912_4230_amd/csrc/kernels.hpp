@@ -607,9 +607,12 @@ template <class R> struct Newton { static constexpr R tol = R(1e-7); };
 template <> struct Newton<double> { static constexpr double tol = 1e-15; };
 
 // |V'| of the implicit velocity V'_a = W_a / (lam_a + mu_a |V'|): Newton on
-// phi(s) = s - sqrt(sum_a W_a^2 / (lam_a + mu_a s)^2) from the Darcy-only
-// value, an upper bound of the root; stops when the update is below the
-// working precision (at most 8 iterations).
+// phi(s) = s - R(s), R(s) = sqrt(sum_a W_a^2 / (lam_a + mu_a s)^2), from the
+// Darcy-only value, an upper bound of the root (at most 8 iterations).
+// Near the root phi' >= 1 and |phi''| = |R''| <= 3 R max_a (mu_a / (lam_a +
+// mu_a s))^2 <= 3 / s, so the error left after an update ds is at most
+// 1.5 ds^2 / s: the loop stops once that bound is below the working
+// precision (tol s), which saves the iteration that would only confirm it.
 template <class R, bool HW>
 __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], const R ilam[3])
 {
@@ -635,7 +638,7 @@ __device__ inline R solve_speed(const R W[3], const R lam[3], const R mu[3], con
             const R ds = fdiv<HW>(phi, dphi);
             s = s - ds;
             s = s > R(0) ? s : R(0);
-            if (!(fabs(ds) > Newton<R>::tol * s)) break;
+            if (!(R(1.5) * ds * ds > Newton<R>::tol * s * s)) break;
         }
     }
     return s;
