@@ -58,6 +58,12 @@ struct FsDev {
     // the last step, whose flag pass 1 clears); written by the last class
     // pass for the next step, all rows set at set-up
     unsigned char *rowlive[2];
+    // per row of 256 cells: nonzero when the class passes have work in it this
+    // step (a conversion flag of pass 1, a mark written by a class pass, or a
+    // wave of pass 1 without liquid or interface cells, whose liveness the last
+    // pass recomputes); the class passes skip the other rows, the last pass
+    // clears it; zero at set-up
+    unsigned char *rowwork;
 };
 
 // List a row for the next pass 1 (buffer buf), once: the first caller claims
@@ -405,8 +411,13 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
         for (int q = 0; q < NQ; ++q) d[q] = R(0);
     }
     if (idx < ncell) stg<uint8_t>(F->w1, idx, flag);
+    // the class passes work on the rows with a flag, and recompute the
+    // liveness of rows that have a wave without liquid or interface cells
+    const bool any_live = __builtin_amdgcn_ballot_w64(live) != 0;
+    if ((__builtin_amdgcn_ballot_w64(flag != 0) != 0 || !any_live) && (threadIdx.x & 63) == 0)
+        stg<uint8_t>(F->rowwork, row, 1);
     // waves made only of gas and solid cells store nothing
-    if (idx < ncell && __builtin_amdgcn_ballot_w64(live) != 0)
+    if (idx < ncell && any_live)
         store_all<S>(L->f[dst], L->fm[dst], L->pstride, idx, d);
     if (__builtin_amdgcn_ballot_w64(cls == FS_IF) != 0 && (threadIdx.x & 63) == 0) fs_list_row(F, dst, row, nrow);
 }
@@ -519,6 +530,20 @@ __device__ inline void for_items(uint32_t mask, uint32_t base, Fn &&fn)
     }
 }
 
+// write mark byte v of cell j and note its row as one with work
+__device__ inline void mark(const FsDev *F, uint32_t j, uint8_t v)
+{
+    stg<uint8_t>(F->w2, j, v);
+    stg<uint8_t>(F->rowwork, j / BLOCK, 1);
+}
+
+// does the row of this thread's cells have work in this step's class passes
+// (the FS_CPT cells of a thread lie in one row)
+__device__ inline bool row_work(const FsTile &t)
+{
+    return t.base < t.ncell && ldg<uint8_t>(t.F->rowwork, t.base / BLOCK) != 0;
+}
+
 __device__ inline Nbr nbr_of(const LatDev *L, uint32_t idx)
 {
     int x, y, z;
@@ -542,10 +567,12 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
             const uint32_t r = ldg<uint32_t>(F->hlist[src], tn);
             if (r < nrow) stg<uint32_t>(F->hpos[src], r, 0u);
         }
-        const u32x4 f = ld16(F->w1, t.base);
-        if (any_byte(f))
-            for (int k = 0; k < FS_CPT; ++k)
-                if (t.base + k < t.ncell && byte_of(f, k) == FS_FILL) mask |= 1u << k;
+        if (row_work(t)) {
+            const u32x4 f = ld16(F->w1, t.base);
+            if (any_byte(f))
+                for (int k = 0; k < FS_CPT; ++k)
+                    if (t.base + k < t.ncell && byte_of(f, k) == FS_FILL) mask |= 1u << k;
+        }
     }
     if (__builtin_amdgcn_ballot_w64(mask != 0u) == 0) return;   // uniform over the wave
     for_items(mask, t.base, [&](uint32_t idx) {
@@ -554,8 +581,8 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
             constexpr int Q = decltype(qc)::value;
             const uint32_t j = shifted<Q, 1>(b);
             const int cj = ldg<uint8_t>(F->cls, j), fj = ldg<uint8_t>(F->w1, j);
-            if (cj == FS_GAS) stg<uint8_t>(F->w2, j, FS_BORN);
-            else if (fj == FS_EMPTY) stg<uint8_t>(F->w2, j, FS_KEEP);
+            if (cj == FS_GAS) mark(F, j, FS_BORN);
+            else if (fj == FS_EMPTY) mark(F, j, FS_KEEP);
         });
     });
 }
@@ -575,7 +602,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
     const int dst = (t.flags & 1) ^ 1;
     if (t.base == 0) stg<uint32_t>(F->hcount[dst ^ 1], 0, 0u);   // the list unlisted by the last pass
     uint32_t mask = 0;
-    if (t.base < t.ncell) {
+    if (row_work(t)) {
         const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base);
         if (any_byte(f) || any_byte(m2))
             for (int k = 0; k < FS_CPT; ++k) {
@@ -592,7 +619,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
             for_links([&](auto qc) {
                 constexpr int Q = decltype(qc)::value;
                 const uint32_t j = shifted<Q, 1>(b);
-                if (ldg<uint8_t>(F->cls, j) == FS_LIQ) stg<uint8_t>(F->w2, j, FS_TO_IF);
+                if (ldg<uint8_t>(F->cls, j) == FS_LIQ) mark(F, j, FS_TO_IF);
             });
         } else {
             // born: a gas cell has no liquid neighbour, so the qualifying
@@ -640,7 +667,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
     const FsTile t = fs_tile(a);
     const FsDev *__restrict__ F = t.F;
     uint32_t mask = 0;
-    if (t.base < t.ncell) {
+    if (row_work(t)) {
         const u32x4 f = ld16(F->w1, t.base);
         if (any_byte(f)) {
             const u32x4 m2 = ld16(F->w2, t.base);
@@ -674,7 +701,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
                 const uint32_t j = shifted<Q, 1>(b);
                 const int cj = ldg<uint8_t>(F->cls, j), mj = ldg<uint8_t>(F->w2, j);
                 if ((cj == FS_IF && !converts(F, j)) || (mj & (FS_BORN | FS_TO_IF)))
-                    stg<uint8_t>(F->w2, j, (uint8_t)(mj | FS_RECV));
+                    mark(F, j, (uint8_t)(mj | FS_RECV));
             });
     });
 }
@@ -710,7 +737,8 @@ __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
     // flagged in this step (pass 1 clears its flag)
     bool keep = false;
     uint32_t mask = 0;
-    if (t.base < t.ncell) {
+    const bool work = row_work(t);
+    if (work) {
         const u32x4 f = ld16(F->w1, t.base), m2 = ld16(F->w2, t.base), c0 = ld16(F->cls, t.base);
         keep = any_byte(f) || any_live(c0) || ((m2.x | m2.y | m2.z | m2.w) & 0x01010101u * FS_BORN) != 0u;
         if (any_byte(f) || any_byte(m2))
@@ -764,13 +792,22 @@ __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
         });
     }
     // one flag per row of BLOCK cells: the BLOCK / FS_CPT consecutive lanes
-    // that cover the row vote, the first of them writes it
+    // that cover a row with work vote, the first of them writes it and clears
+    // the row's work byte; a row without work changed no class and has no
+    // flag, so it keeps the flag pass 1 read
     constexpr int TPR = BLOCK / FS_CPT;
     static_assert(64 % TPR == 0, "a row's lanes lie in one wave");
     const uint64_t vote = __builtin_amdgcn_ballot_w64(keep);
     const int lane = threadIdx.x & 63;
-    if (lane % TPR == 0 && t.base < t.ncell)
-        stg<uint8_t>(F->rowlive[dst], t.base / BLOCK, ((vote >> lane) & ((uint64_t(1) << TPR) - 1)) != 0 ? 1 : 0);
+    if (lane % TPR == 0 && t.base < t.ncell) {
+        const uint32_t row = t.base / BLOCK;
+        if (work) {
+            stg<uint8_t>(F->rowlive[dst], row, ((vote >> lane) & ((uint64_t(1) << TPR) - 1)) != 0 ? 1 : 0);
+            stg<uint8_t>(F->rowwork, row, 0);
+        } else {
+            stg<uint8_t>(F->rowlive[dst], row, ldg<uint8_t>(F->rowlive[dst ^ 1], row));
+        }
+    }
 }
 
 // Moment steps, after pass 5 (one thread per cell, the step grid): rho, V'
@@ -881,6 +918,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const 
         stg<uint32_t>(F->hpos[1], blockIdx.x, 0u);
         stg<uint8_t>(F->rowlive[0], blockIdx.x, 1);
         stg<uint8_t>(F->rowlive[1], blockIdx.x, 1);
+        stg<uint8_t>(F->rowwork, blockIdx.x, 0);
         if (blockIdx.x == 0) {
             stg<uint32_t>(F->hcount[0], 0, 0u);
             stg<uint32_t>(F->hcount[1], 0, 0u);

@@ -182,8 +182,9 @@ Layout layout(const lbm_desc *d)
     const bool fs = d->physics == LBM_FREESURF;
     // free surface: the FsDev block (+ the lost-mass counter), three byte
     // planes, five double planes (m, two of lambda, rho, share) and the 3
-    // double planes of V', and two launch-order sets (row list, per-row
-    // positions, count, per-row live flags)
+    // double planes of V', two launch-order sets (row list, per-row
+    // positions, count, per-row live flags) and the per-row work flags of the
+    // class passes
     L.fs = o;        if (fs) o = align_up(o + sizeof(FsDev) + sizeof(double));
     L.fs_cls = o;    if (fs) o = align_up(o + n);
     L.fs_w1 = o;     if (fs) o = align_up(o + n);
@@ -194,7 +195,7 @@ Layout layout(const lbm_desc *d)
     L.fs_share = o;  if (fs) o = align_up(o + n * sizeof(double));
     L.fs_u = o;      if (fs) o = align_up(o + 3 * n * sizeof(double));
     const size_t rows4 = align_up((n + BLOCK - 1) / BLOCK * 4), rows1 = align_up((n + BLOCK - 1) / BLOCK);
-    L.fs_hot = o;    if (fs) o = align_up(o + 2 * (2 * rows4 + 256 + rows1));
+    L.fs_hot = o;    if (fs) o = align_up(o + 2 * (2 * rows4 + 256 + rows1) + rows1);
     // further solutes: the MsDev block, per solute two population copies and,
     // split storage, two mass planes
     const int nsx = extra_species(d);
@@ -646,6 +647,7 @@ void setup_handle(lbm_sim *h, const lbm_desc *d, void *dev_workspace, size_t ws_
             F.hcount[c] = reinterpret_cast<uint32_t *>(base + 2 * rows4);
             F.rowlive[c] = reinterpret_cast<unsigned char *>(base + 2 * rows4 + 256);
         }
+        F.rowwork = reinterpret_cast<unsigned char *>(w + L.fs_hot + 2 * (2 * rows4 + 256 + rows1));
         D.fs = w + L.fs;
     }
     D.partials = reinterpret_cast<double *>(w + L.partials);
