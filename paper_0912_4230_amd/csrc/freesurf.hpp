@@ -18,8 +18,8 @@
 //   k_fs_moments     moments and FP64 diagnostics (moment steps only)
 // Liquid cells cost one byte read and one byte written more than the
 // single-fluid step; gas cells are skipped (waves made only of gas cells
-// store nothing); the class passes read byte planes, 16 cells per thread, and
-// work only next to conversions.
+// store nothing); the class passes read byte planes, 16 cells per thread, of
+// the rows flagged as having work, and work only next to conversions.
 #pragma once
 
 #include <type_traits>
