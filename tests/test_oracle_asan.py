@@ -65,7 +65,9 @@ def test_oracle_under_sanitizers(tmp_path):
                     "-fPIC", "-shared", "-o", lib, os.path.join(ROOT, "oracle", "lbm_oracle.c"), "-lm"], check=True)
     script = tmp_path / "child.py"
     script.write_text(CHILD)
-    env = dict(os.environ, LD_PRELOAD=os.path.realpath(asan), OMP_NUM_THREADS="2",
+    # the sanitizer runtime goes first; anything already preloaded stays
+    pre = os.path.realpath(asan) + (":" + os.environ["LD_PRELOAD"] if os.environ.get("LD_PRELOAD") else "")
+    env = dict(os.environ, LD_PRELOAD=pre, OMP_NUM_THREADS="2",
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([sys.executable, str(script), lib, ROOT, ROOT, os.path.join(ROOT, "tests")], env=env,
