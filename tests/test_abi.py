@@ -129,6 +129,11 @@ def test_create_checks_before_gpu():
     assert L.lbm_moments(None, None, None, None, None) == B.LBM_EINVAL
     assert L.lbm_destroy(None) == B.LBM_EINVAL
     assert L.lbm_steps_done(None) == -1
+    # checkpoint calls on a NULL handle
+    buf = (C.c_ubyte * 64)()
+    assert L.lbm_state_bytes(None) == 0
+    assert L.lbm_save_state(None, buf, C.c_size_t(64)) == B.LBM_EINVAL
+    assert L.lbm_load_state(None, buf, C.c_size_t(64)) == B.LBM_EINVAL
 
 
 @pytest.mark.parametrize("storage,nz", [(B.LBM_F64, 255), (B.LBM_F32, 511), (B.LBM_BF16_DEV, 1023)])
