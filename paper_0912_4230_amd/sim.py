@@ -45,6 +45,26 @@ def make_desc(p: I.Problem, storage: int = B.LBM_F32, diag_every: int = 0) -> B.
     return d
 
 
+def check_fields(p: I.Problem) -> None:
+    """The per-cell arrays of a problem have the shapes the kernels read
+    (lbm_set_medium takes device pointers without sizes, so a short array
+    would be read past its end): eps (nz,ny,nx); K^-1 3 planes, or 6 for a
+    full tensor; rho0 (nz,ny,nx); V0 3 planes; c0 one plane, or one per solute
+    in the miscible model with several solutes; the obstacle mask (nz,ny,nx).
+    Raises ValueError."""
+    nx, ny, nz = (int(v) for v in p.shape)
+    cell = (nz, ny, nx)
+    ns = p.nspecies if p.physics == I.MISCIBLE else 1
+    want = {"eps": cell, "kinv": ((6 if p.full_tensor else 3),) + cell, "rho0": cell, "vel0": (3,) + cell,
+            "c0": cell if ns == 1 else (ns,) + cell}
+    if p.solid is not None:
+        want["solid"] = cell
+    for name, shape in want.items():
+        a = getattr(p, name)
+        if a is None or tuple(np.shape(a)) != shape:
+            raise ValueError(f"{name}: shape {None if a is None else tuple(np.shape(a))}, expected {shape}")
+
+
 def real_dtype(storage: int):
     import torch
     return torch.float64 if storage == B.LBM_F64 else torch.float32
@@ -64,6 +84,7 @@ class Simulation:
         if isinstance(storage, str):
             storage = B.STORAGE_NAMES[storage]
         p = problem.fill_defaults()
+        check_fields(p)
         self.problem = p
         self.storage = storage
         self.device = torch.device(device)

@@ -3,6 +3,7 @@ spruce-like medium and the request stream."""
 import math
 
 import numpy as np
+import pytest
 
 from paper_0912_4230_amd import inputs as I
 
@@ -84,3 +85,23 @@ def test_block_obstacles_crop_and_fraction():
     # whole 4^3 cubes
     c = m[:, :, 4:60].reshape(16, 4, 16, 4, 14, 4)
     assert np.all(c.min(axis=(1, 3, 5)) == c.max(axis=(1, 3, 5)))
+
+
+def test_field_shapes_checked_before_upload():
+    """Simulation refuses arrays that do not have the shapes the kernels
+    read (the C ABI takes device pointers without sizes): here the initial
+    concentrations of a three-solute problem with one plane too few."""
+    from paper_0912_4230_amd.sim import check_fields
+    p = I.miscible(shape=(12, 10, 8), seed=0)
+    p.species_tau_d = (0.65, 0.8)
+    p.c0 = np.zeros((3, 8, 10, 12))
+    check_fields(p)
+    p.c0 = np.zeros((2, 8, 10, 12))
+    with pytest.raises(ValueError, match="c0"):
+        check_fields(p)
+    q = I.miscible(shape=(12, 10, 8), seed=0)
+    q.kinv = q.kinv[:2]
+    with pytest.raises(ValueError, match="kinv"):
+        check_fields(q)
+    r = I.miscible(shape=(12, 10, 8), seed=0, ring_angle=45.0)
+    check_fields(r)
