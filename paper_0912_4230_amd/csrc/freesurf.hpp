@@ -70,7 +70,7 @@ struct FsDev {
 // it, takes a position and records it; later callers find it claimed.
 // Positions stay below the row count nrow (a row is listed at most once
 // until it is unlisted); the bound on the store guards the list regardless.
-__device__ inline void fs_list_row(const FsDev *F, int buf, uint32_t row, uint32_t nrow)
+__device__ inline void fs_list_row(const GL FsDev *F, int buf, uint32_t row, uint32_t nrow)
 {
     if (atomicCAS(F->hpos[buf] + row, 0u, ~0u) == 0u) {
         const uint32_t pos = atomicAdd(F->hcount[buf], 1u);
@@ -79,7 +79,13 @@ __device__ inline void fs_list_row(const FsDev *F, int buf, uint32_t row, uint32
     }
 }
 
-__device__ inline const FsDev *fs_of(const LatDev *L) { return static_cast<const FsDev *>(L->fs); }
+// The free-surface block lives in the workspace (global memory); naming its
+// address space lets the compiler read its fields with scalar loads instead
+// of a vector round trip per field.
+__device__ inline const GL FsDev *fs_of(const LatDev *L)
+{
+    return static_cast<const GL FsDev *>((const GL void *)L->fs);
+}
 
 // f(std::integral_constant<int, Q>) for Q = 1 .. 18
 template <int Q = 1, class Fn>
@@ -157,7 +163,7 @@ __device__ inline void equilibrium(R rho, const R u[3], R ie, R *e)
 
 struct FsCell {
     const LatDev *L;
-    const FsDev *F;
+    const GL FsDev *F;
     int l, lb, flags;
     uint32_t idx, ncell;
 };
@@ -189,7 +195,7 @@ __device__ inline void coords(const LatDev *L, uint32_t idx, int &x, int &y, int
 
 // fill fraction of the step's start of a cell of class c (1 liquid, 0 gas,
 // m / rho interface)
-__device__ inline double fs_lambda(const FsDev *F, int c, uint32_t j, int src)
+__device__ inline double fs_lambda(const GL FsDev *F, int c, uint32_t j, int src)
 {
     return c == FS_LIQ ? 1.0 : (c == FS_IF ? ldg<double>(F->lam[src], j) : 0.0);
 }
@@ -235,7 +241,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
     [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     FsCell c = fs_cell(a);
     const LatDev *__restrict__ L = c.L;
-    const FsDev *__restrict__ F = c.F;
+    const GL FsDev *__restrict__ F = c.F;
     const int src = c.flags & 1, dst = src ^ 1;
     const uint32_t nrow = (c.ncell + BLOCK - 1) / BLOCK;
     const uint32_t cap = uint32_t(a.blk_start[c.l + 1] - a.blk_start[c.l]) - nrow;
@@ -443,7 +449,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct FsTile {
     const LatDev *L;
-    const FsDev *F;
+    const GL FsDev *F;
     int flags;
     uint32_t base, ncell;
 };
@@ -531,7 +537,7 @@ __device__ inline void for_items(uint32_t mask, uint32_t base, Fn &&fn)
 }
 
 // write mark byte v of cell j and note its row as one with work
-__device__ inline void mark(const FsDev *F, uint32_t j, uint8_t v)
+__device__ inline void mark(const GL FsDev *F, uint32_t j, uint8_t v)
 {
     stg<uint8_t>(F->w2, j, v);
     stg<uint8_t>(F->rowwork, j / BLOCK, 1);
@@ -556,7 +562,7 @@ __device__ inline Nbr nbr_of(const LatDev *L, uint32_t idx)
 __global__ __launch_bounds__(BLOCK) void k_fs_mark_fill(const BatchArgs a)
 {
     const FsTile t = fs_tile(a);
-    const FsDev *__restrict__ F = t.F;
+    const GL FsDev *__restrict__ F = t.F;
     uint32_t mask = 0;
     if (t.base < t.ncell) {
         // the launch-order list pass 1 has just used serves the next step
@@ -598,7 +604,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
     [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsTile t = fs_tile(a);
     const LatDev *__restrict__ L = t.L;
-    const FsDev *__restrict__ F = t.F;
+    const GL FsDev *__restrict__ F = t.F;
     const int dst = (t.flags & 1) ^ 1;
     if (t.base == 0) stg<uint32_t>(F->hcount[dst ^ 1], 0, 0u);   // the list unlisted by the last pass
     uint32_t mask = 0;
@@ -653,7 +659,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_mark_empty(const BatchArgs a)
 }
 
 // does the neighbour j convert (fill, or empty after all)?
-__device__ inline bool converts(const FsDev *F, uint32_t j)
+__device__ inline bool converts(const GL FsDev *F, uint32_t j)
 {
     const int f = ldg<uint8_t>(F->w1, j);
     return f == FS_FILL || (f == FS_EMPTY && !(ldg<uint8_t>(F->w2, j) & FS_KEEP));
@@ -665,7 +671,7 @@ __device__ inline bool converts(const FsDev *F, uint32_t j)
 __global__ __launch_bounds__(BLOCK) void k_fs_excess(const BatchArgs a)
 {
     const FsTile t = fs_tile(a);
-    const FsDev *__restrict__ F = t.F;
+    const GL FsDev *__restrict__ F = t.F;
     uint32_t mask = 0;
     if (row_work(t)) {
         const u32x4 f = ld16(F->w1, t.base);
@@ -730,7 +736,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_final(const BatchArgs a)
     using R = typename Codec<S>::R;
     const FsTile t = fs_tile(a);
     const LatDev *__restrict__ L = t.L;
-    const FsDev *__restrict__ F = t.F;
+    const GL FsDev *__restrict__ F = t.F;
     const int dst = (t.flags & 1) ^ 1;
     // do this thread's cells keep their row in the next pass 1: a cell that is
     // liquid or interface after this step (it was, or was born), or one
@@ -821,7 +827,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_moments(const BatchArgs a)
     [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const FsCell c = fs_cell(a);
     const LatDev *__restrict__ L = c.L;
-    const FsDev *__restrict__ F = c.F;
+    const GL FsDev *__restrict__ F = c.F;
     const uint32_t idx = c.idx, ncell = c.ncell;
     const int dst = (c.flags & 1) ^ 1;
     double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_classes(const LatDev *L, cons
 {
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= uint32_t(L->ncell)) return;
-    const FsDev *F = fs_of(L);
+    const GL FsDev *F = fs_of(L);
     int x, y, z, face;
     coords(L, idx, x, y, z);
     const int type = cell_type(L, x, y, z, link_word(L, idx), face);
@@ -875,7 +881,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_init_state(const LatDev *L, const 
 {
     const uint32_t ncell = L->ncell;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
-    const FsDev *F = fs_of(L);
+    const GL FsDev *F = fs_of(L);
     double part[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (idx < ncell) {
         int cls = ldg<uint8_t>(F->w1, idx);
@@ -939,7 +945,7 @@ __global__ __launch_bounds__(BLOCK) void k_fs_export(const LatDev *L, int src, u
     [[maybe_unused]] constexpr bool HW = HwMath<S>::value;
     const uint32_t idx = blockIdx.x * BLOCK + threadIdx.x;
     if (idx >= uint32_t(L->ncell)) return;
-    const FsDev *F = fs_of(L);
+    const GL FsDev *F = fs_of(L);
     const int c = ldg<uint8_t>(F->cls, idx);
     if (cls) cls[idx] = (unsigned char)c;
     if (mass) {

@@ -93,7 +93,11 @@ struct MsDev {
     double face_conc[MAXSPX][6];
 };
 
-__device__ inline const MsDev *ms_of(const LatDev *L) { return static_cast<const MsDev *>(L->ms); }
+// the further-solute block (global memory, read with scalar loads)
+__device__ inline const GL MsDev *ms_of(const LatDev *L)
+{
+    return static_cast<const GL MsDev *>((const GL void *)L->ms);
+}
 
 // Arguments of one batched launch: lattice l owns logical blocks
 // [blk_start[l], blk_start[l+1]).  flags bit 0: copy holding step n; bit 1:
@@ -1121,7 +1125,7 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(StepWaves<PHYS, S, 
     if constexpr (MS) {
         // further solutes: the first solute's update with their own D, tau_d
         // and reservoir concentrations, one at a time
-        const MsDev *X = ms_of(L);
+        const GL MsDev *X = ms_of(L);
         const int nsx = X ? X->nsx : 0;
         for (int k = 0; k < nsx; ++k) {
             R hk[NQ];
@@ -1530,7 +1534,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InitArgs<typename Codec<S>
     if constexpr (PHYS == PH_MISCIBLE) {
         // further solutes: h = h^eq(eps C0_k, V0 + D_k grad(eps)/eps) from
         // plane k of c0, as the first solute; reservoirs w eps C_bc,k
-        const MsDev *X = ms_of(L);
+        const GL MsDev *X = ms_of(L);
         const int nsx = X ? X->nsx : 0;
         for (int k = 0; k < nsx; ++k) {
             R hk[NQ], Ck = 0;
@@ -1652,7 +1656,7 @@ __global__ __launch_bounds__(BLOCK) void k_export(const LatDev *L, int which, in
             return;
         }
     }
-    const MsDev *X = ms_of(L);
+    const GL MsDev *X = ms_of(L);
     const void *P = which == 0 ? L->f[src] : (which == 1 ? L->h[src] : X->h[which - 2][src]);
     const void *M = which == 0 ? L->fm[src] : (which == 1 ? L->hm[src] : X->hm[which - 2][src]);
     const R m = Codec<S>::split ? ldg<R>(M, idx) : R(0);
