@@ -210,17 +210,16 @@ __device__ inline double fs_lambda(const GL FsDev *F, int c, uint32_t j, int src
 // solid neighbour takes lambda(x)); interface cells store m and rho and flag
 // FILL / EMPTY.
 // Waves per SIMD the stream/collide pass is compiled for.  Without tensor or
-// surface tension: FP32, BF16 deviations and FP16 split take 7 waves (72
-// VGPRs, 20-48 bytes of spill per lane), BF16 split 6, FP16 deviations 5.
-// On the 256^3 penetration step, 7 waves against 6 measured FP32 -1.7%, BF16
-// -5.3%, FP16 split -3%, but BF16 split +4% and FP16 deviations +6% (at 6,
-// the 16-bit forms had been 13% faster than at their natural 4-5 waves).
+// surface tension: FP32, BF16 and FP16 deviations and both split forms take 7
+// waves (72 VGPRs, 0-20 bytes of spill per lane), FP16 deviations 6.  On the
+// 256^3 penetration step, one wave more measured FP32 +13%, FP16 split +7%,
+// BF16 +0.5%, and BF16 split (6 -> 7) -3%, FP16 deviations (5 -> 6) -7%.
 // Every other form keeps the compiler's choice.
 template <class S, bool FT, bool ST> struct FsWaves { static constexpr int value = 1; };
 template <> struct FsWaves<bf16_t, false, false> { static constexpr int value = 7; };
-template <> struct FsWaves<bf16s_t, false, false> { static constexpr int value = 6; };
+template <> struct FsWaves<bf16s_t, false, false> { static constexpr int value = 7; };
 template <> struct FsWaves<f16s_t, false, false> { static constexpr int value = 7; };
-template <> struct FsWaves<f16_t, false, false> { static constexpr int value = 5; };
+template <> struct FsWaves<f16_t, false, false> { static constexpr int value = 6; };
 template <> struct FsWaves<float, false, false> { static constexpr int value = 7; };
 
 //
