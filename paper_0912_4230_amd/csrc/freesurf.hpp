@@ -276,7 +276,9 @@ __global__ PLBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(FsWaves<S, FT, ST>:
     unsigned char flag = 0;
     if (live) {
         const Nbr b = neighbours(L, x, y, z, lw);
-        pull_all<S>(L->f[src], L->fm[src], L->pstride, idx, b, d);
+        // split codecs: the 19 mass loads (sharing the x-links' masses across
+        // the wave measured 4% slower here in BF16, which spills at 7 waves)
+        pull_all<S, false>(L->f[src], L->fm[src], L->pstride, idx, b, d);
         const R eps = L->uniform_eps ? R(L->eps_u) : ldg<R>(L->eps, idx);
         const R ie = rcp<HW>(eps);
         double m = 0.0;

@@ -346,8 +346,9 @@ constexpr int pair_lo() { return Q < opp(Q) ? Q : opp(Q); }
 // Split codecs: a population is w_q m + r_q, with the per-cell mass m in an
 // FP32 plane M and the remainder r_q in the 16-bit planes; a bounced link
 // takes both from the cell itself.  BB = false: no cell of the wave has a
-// solid upstream neighbour.
-template <class S, bool BB, int Q = 0>
+// solid upstream neighbour.  XL: the masses of the links with c_x != 0 are
+// not loaded here (xl_masses).
+template <class S, bool BB, bool XL, int Q = 0>
 __device__ inline void split_loads(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
                                    typename Codec<S>::R *r, typename Codec<S>::R *m)
 {
@@ -359,20 +360,104 @@ __device__ inline void split_loads(const void *P, const void *M, uint32_t n, uin
     } else {
         const uint32_t src = shifted<Q, -1>(b);
         r[Q] = Codec<S>::load(at(plane<S>(P, n, Q), src));
-        m[Q] = ldg<R>(M, src);
+        if constexpr (!XL || cx(Q) == 0) m[Q] = ldg<R>(M, src);
     }
-    if constexpr (Q + 1 < NQ) split_loads<S, BB, Q + 1>(P, M, n, idx, b, r, m);
+    if constexpr (Q + 1 < NQ) split_loads<S, BB, XL, Q + 1>(P, M, n, idx, b, r, m);
 }
 
-template <class S, bool BB, int Q = 0>
+// Split codecs, waves without bounce-back: the upstream mass of a link with
+// c_x = +1 (-1) is the one that the lane below (above) loads for the link of
+// the same row with c_x = 0, when that lane holds the cell x - 1 (x + 1) of
+// this cell's row: it is taken across the wave by a DPP shift of one lane
+// instead of being loaded again (9 mass loads instead of 19).  A lane whose
+// neighbour lane is outside the wave, inactive, holds another cell or lies in
+// another row (the row ends or wraps there) needs that mass from memory: every
+// lane issues one more load per row, with the others and before the shifts,
+// at the outer mass it needs (or its row's own, which it has), and a wave in
+// which some lane needs both outer masses of its rows that way takes the
+// general path.  Timed at 256^3, the split miscible step ran 4-5% faster
+// than with the 19 loads; staging the rows in LDS behind a barrier, or
+// loading the outer masses under per-lane branches, ran slower than that.
+struct XLanes {
+    bool lo, hi;   // the lane loads its mass at x - 1 (lo) or x + 1 (hi)
+};
+
+template <int CTRL>
+__device__ inline float lane_shift(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ inline f32x2_t lane_shift(f32x2_t v)
+{
+    return f32x2_t{lane_shift<CTRL>(v.x), lane_shift<CTRL>(v.y)};
+}
+
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane i reads lane i + 1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane i reads lane i - 1
+
+__device__ inline XLanes xlanes(const Nbr &b, uint32_t idx)
+{
+    const uint64_t act = __builtin_amdgcn_read_exec();
+    const int lane = int(__lane_id());
+    const uint32_t below = uint32_t(__builtin_amdgcn_update_dpp(0, int(idx), DPP_WAVE_SHR1, 0xf, 0xf, false));
+    const uint32_t above = uint32_t(__builtin_amdgcn_update_dpp(0, int(idx), DPP_WAVE_SHL1, 0xf, 0xf, false));
+    XLanes x;
+    x.lo = lane == 0 || !((act >> ((lane - 1) & 63)) & 1u) || below + 1u != idx || b.xm + 1u != b.x0;
+    x.hi = lane == 63 || !((act >> ((lane + 1) & 63)) & 1u) || above != idx + 1u || b.x0 + 1u != b.xp;
+    return x;
+}
+
+// does a lane of the wave need both outer masses of its rows from memory?
+__device__ inline bool xl_general(const XLanes &x) { return __builtin_amdgcn_ballot_w64(x.lo && x.hi) != 0; }
+
+template <int CX, int CY, int CZ>
+__host__ __device__ constexpr int link_of()
+{
+    for (int q = 0; q < NQ; ++q)
+        if (cx(q) == CX && cy(q) == CY && cz(q) == CZ) return q;
+    return -1;
+}
+
+// the one load per row (kept in slot Q of the row's c_x = +1 link)
+template <class T, int Q = 1>
+__device__ inline void xl_loads(const void *M, const Nbr &b, const XLanes &x, T *e)
+{
+    if constexpr (cx(Q) > 0) {
+        constexpr int qm = link_of<-1, cy(Q), cz(Q)>(), q0 = link_of<0, cy(Q), cz(Q)>();
+        const uint32_t lo = shifted<Q, -1>(b), hi = shifted<qm, -1>(b), own = shifted<q0, -1>(b);
+        e[Q] = ldg<T>(M, x.lo ? lo : (x.hi ? hi : own));
+    }
+    if constexpr (Q + 1 < NQ) xl_loads<T, Q + 1>(M, b, x, e);
+}
+
+template <class T, int Q = 1>
+__device__ inline void xl_masses(const XLanes &x, const T *e, T *m)
+{
+    if constexpr (cx(Q) > 0) {
+        constexpr int qm = link_of<-1, cy(Q), cz(Q)>(), q0 = link_of<0, cy(Q), cz(Q)>();
+        const T lo = lane_shift<DPP_WAVE_SHR1>(m[q0]), hi = lane_shift<DPP_WAVE_SHL1>(m[q0]);
+        m[Q] = x.lo ? e[Q] : lo;
+        m[qm] = x.hi ? e[Q] : hi;
+    }
+    if constexpr (Q + 1 < NQ) xl_masses<T, Q + 1>(x, e, m);
+}
+
+template <class S, bool BB, bool XL = false, int Q = 0>
 __device__ inline void pull_each(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
-                                 typename Codec<S>::R *out)
+                                 typename Codec<S>::R *out, const XLanes &xl = XLanes{})
 {
     using R = typename Codec<S>::R;
     if constexpr (Codec<S>::split) {
         // all remainder and mass loads first, then the decode
         R r[NQ], m[NQ];
-        split_loads<S, BB>(P, M, n, idx, b, r, m);
+        split_loads<S, BB, XL>(P, M, n, idx, b, r, m);
+        if constexpr (XL) {
+            R e[NQ];
+            xl_loads<R>(M, b, xl, e);
+            xl_masses<R>(xl, e, m);
+        }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) out[q] = fma(weight<R>(q), m[q], r[q]);
     } else {
@@ -382,18 +467,25 @@ __device__ inline void pull_each(const void *P, const void *M, uint32_t n, uint3
         } else {
             out[Q] = Codec<S>::load(at(plane<S>(P, n, Q), shifted<Q, -1>(b)));
         }
-        if constexpr (Q + 1 < NQ) pull_each<S, BB, Q + 1>(P, M, n, idx, b, out);
+        if constexpr (Q + 1 < NQ) pull_each<S, BB, false, Q + 1>(P, M, n, idx, b, out);
     }
 }
 
 // Pull of one lattice.  Waves without a solid upstream neighbour (all but a
-// thin layer next to walls and obstacles) take the path without selects.
-template <class S>
+// thin layer next to walls and obstacles) take the path without selects (and
+// with the split codecs, XS, the one that shares the x-links' masses).
+template <class S, bool XS = true>
 __device__ inline void pull_all(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
                                 typename Codec<S>::R *out)
 {
-    if (wave_near_solid(b)) pull_each<S, true>(P, M, n, idx, b, out);
-    else pull_each<S, false>(P, M, n, idx, b, out);
+    if constexpr (Codec<S>::split && XS) {
+        const XLanes xl = xlanes(b, idx);
+        if (wave_near_solid(b) || xl_general(xl)) pull_each<S, true>(P, M, n, idx, b, out);
+        else pull_each<S, false, true>(P, M, n, idx, b, out, xl);
+    } else {
+        if (wave_near_solid(b)) pull_each<S, true>(P, M, n, idx, b, out);
+        else pull_each<S, false>(P, M, n, idx, b, out);
+    }
 }
 
 template <class S, int Q = 0>
@@ -441,7 +533,7 @@ __device__ inline void store_all(void *P, void *M, uint32_t n, uint32_t idx, con
 template <int PHYS, class S>
 constexpr bool paired_v = PHYS == PH_MISCIBLE && sizeof(S) == 2;
 
-template <class S, bool BB, int Q = 0>
+template <class S, bool BB, bool XL, int Q = 0>
 __device__ inline void pair_loads(const void *P, const void *M, uint32_t n, uint32_t idx, const Nbr &b,
                                   typename Codec<S>::R *a, typename Codec<S>::R *c, f32x2_t *m)
 {
@@ -453,9 +545,9 @@ __device__ inline void pair_loads(const void *P, const void *M, uint32_t n, uint
     } else {
         const uint32_t src = shifted<Q, -1>(b);
         PairCodec<S>::load(at(plane<W>(P, n, Q), src), a[Q], c[Q]);
-        if constexpr (Codec<S>::split) m[Q] = ldg<f32x2_t>(M, src);
+        if constexpr (Codec<S>::split && (!XL || cx(Q) == 0)) m[Q] = ldg<f32x2_t>(M, src);
     }
-    if constexpr (Q + 1 < NQ) pair_loads<S, BB, Q + 1>(P, M, n, idx, b, a, c, m);
+    if constexpr (Q + 1 < NQ) pair_loads<S, BB, XL, Q + 1>(P, M, n, idx, b, a, c, m);
 }
 
 // Pull of both lattices from paired planes (a: f, c: h).
@@ -465,8 +557,20 @@ __device__ inline void pull_pair(const void *P, const void *M, uint32_t n, uint3
 {
     using R = typename Codec<S>::R;
     f32x2_t m[Codec<S>::split ? NQ : 1];
-    if (wave_near_solid(b)) pair_loads<S, true>(P, M, n, idx, b, a, c, m);
-    else pair_loads<S, false>(P, M, n, idx, b, a, c, m);
+    if constexpr (Codec<S>::split) {
+        const XLanes xl = xlanes(b, idx);
+        if (wave_near_solid(b) || xl_general(xl)) {
+            pair_loads<S, true, false>(P, M, n, idx, b, a, c, m);
+        } else {
+            pair_loads<S, false, true>(P, M, n, idx, b, a, c, m);
+            f32x2_t e[NQ];
+            xl_loads<f32x2_t>(M, b, xl, e);
+            xl_masses<f32x2_t>(xl, e, m);
+        }
+    } else {
+        if (wave_near_solid(b)) pair_loads<S, true, false>(P, M, n, idx, b, a, c, m);
+        else pair_loads<S, false, false>(P, M, n, idx, b, a, c, m);
+    }
     if constexpr (Codec<S>::split) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
