@@ -432,6 +432,11 @@ __device__ inline void xl_loads(const void *M, const Nbr &b, const XLanes &x, T 
     if constexpr (Q + 1 < NQ) xl_loads<T, Q + 1>(M, b, x, e);
 }
 
+// Both shifts of a row are computed before its selects, where every lane of
+// the pull is active.  Written inside a select (x.lo ? e : shift), a shift
+// was moved by hipcc into the branch it made of the select, ran there with
+// the lanes of x.lo masked off and read them: wrong masses wherever a row
+// ends inside a wave (tests/test_gpu_split_rows.py covers such rows).
 template <class T, int Q = 1>
 __device__ inline void xl_masses(const XLanes &x, const T *e, T *m)
 {
@@ -1023,11 +1028,12 @@ __device__ inline void diag_contrib(double v[NPART], R rho, const R u[3], R C, R
 // Waves per SIMD the step is compiled for.  The miscible step with plain
 // 16-bit storage (diagonal K, one solute) fits in 95 VGPRs at 5 waves without
 // spills and runs 5-18% faster there at 256^3 and 7-9% at 512^3.  The split
-// forms (19 pair words and 19 mass pairs per pull) take 104-105 VGPRs and run
-// at 4 waves: forced to 5 they spill, and issuing their pull in two halves to
-// fit 5 waves measured 3% slower.  Every other form keeps the compiler's own
-// choice (1 = no constraint; the FP32 and FP64 code is the same as without
-// the attribute).
+// forms (19 pair words and 9 + 5 mass-pair loads per pull) take 100-104 VGPRs
+// and run at 4 waves: forced to 5, FP16 split spills a little and runs as fast,
+// BF16 split spills more and runs 17% slower (with 19 mass loads both spilled,
+// and issuing the pull in two halves to fit 5 waves measured 3% slower).
+// Every other form keeps the compiler's own choice (1 = no constraint; the
+// FP32 and FP64 code is the same as without the attribute).
 template <int PHYS, class S, bool FT, bool MS> struct StepWaves { static constexpr int value = 1; };
 template <> struct StepWaves<PH_MISCIBLE, bf16_t, false, false> { static constexpr int value = 5; };
 template <> struct StepWaves<PH_MISCIBLE, f16_t, false, false> { static constexpr int value = 5; };
