@@ -196,21 +196,25 @@ def _fs_one_step(p, n0, storage):
     return r
 
 
+@pytest.mark.parametrize("n0", [8, 100])
 @pytest.mark.parametrize("storage,pop_tol,mass_tol", [("f32", 2e-7, 1e-7), ("bf16", 3e-4, 1e-6)])
-def test_free_surface_penetration_256_one_step(storage, pop_tol, mass_tol):
+def test_free_surface_penetration_256_one_step(storage, pop_tol, mass_tol, n0):
     """The free-surface bench workload (penetration of the 256^3 porous box,
     liquid in the upper half) in the bench's launch configuration, past the
-    initial conversion of the interface (100 steps): the GPU state (populations,
-    classes, masses, fill fractions) is loaded into the FP64 oracle, which takes
-    the next step over the whole box (Sec. 3: mass exchange, Eq. equilempty,
-    conversions, excess).  The cell classes must be identical everywhere; the
-    populations of the live cells, the masses and the fill fractions of the
-    interface cells must agree within the bounds (the oracle computes in FP64
-    from the stored, rounded state, so the differences are one step's rounding
-    of the storage format)."""
-    r = _fs_one_step(I.penetration(shape=(256, 256, 256), seed=0), 100, storage)
+    initial conversion of the interface (100 steps), and at step 9, in which the
+    front advances over the whole box (thousands of gas cells become interface
+    cells): the GPU state (populations, classes, masses, fill fractions) is
+    loaded into the FP64 oracle, which takes the next step over the whole box
+    (Sec. 3: mass exchange, Eq. equilempty, conversions, excess).  The cell
+    classes must be identical everywhere; the populations of the live cells,
+    the masses and the fill fractions of the interface cells must agree within
+    the bounds (the oracle computes in FP64 from the stored, rounded state, so
+    the differences are one step's rounding of the storage format)."""
+    r = _fs_one_step(I.penetration(shape=(256, 256, 256), seed=0), n0, storage)
     assert r["class_mismatch"] == 0
     assert r["interface"] > 10000
+    if n0 == 8:
+        assert r["born"] > 1000
     assert r["df"] < pop_tol and r["dm"] < mass_tol and r["dl"] < mass_tol
     assert r["lost"] == (0.0, 0.0)
 
