@@ -9,6 +9,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libporolbm.so")
 
@@ -196,15 +198,26 @@ def lbm_state_bytes(h) -> int:
     return int(lib().lbm_state_bytes(h))
 
 
+def _host_bytes(buf, writable: bool):
+    """buf as one contiguous run of host bytes for the library, which reads or
+    writes buf.nbytes bytes from its first element."""
+    if not isinstance(buf, np.ndarray) or buf.dtype != np.uint8 or not buf.flags.c_contiguous:
+        raise ValueError("checkpoint buffers are C-contiguous numpy uint8 arrays")
+    if writable and not buf.flags.writeable:
+        raise ValueError("the checkpoint buffer is read-only")
+    return C.c_void_p(buf.ctypes.data), C.c_size_t(buf.nbytes)
+
+
 def lbm_save_state(h, buf) -> int:
-    """Write the checkpoint of h into buf (a writable numpy uint8 array of at
-    least lbm_state_bytes(h) bytes)."""
-    return _check(lib().lbm_save_state(h, C.c_void_p(buf.ctypes.data), C.c_size_t(buf.nbytes)), "lbm_save_state")
+    """Write the checkpoint of h into buf (a writable, C-contiguous numpy uint8
+    array of at least lbm_state_bytes(h) bytes)."""
+    return _check(lib().lbm_save_state(h, *_host_bytes(buf, True)), "lbm_save_state")
 
 
 def lbm_load_state(h, buf) -> int:
-    """Replace h's state by the checkpoint in buf (a numpy uint8 array)."""
-    return _check(lib().lbm_load_state(h, C.c_void_p(buf.ctypes.data), C.c_size_t(buf.nbytes)), "lbm_load_state")
+    """Replace h's state by the checkpoint in buf (a C-contiguous numpy uint8
+    array)."""
+    return _check(lib().lbm_load_state(h, *_host_bytes(buf, False)), "lbm_load_state")
 
 
 def lbm_destroy(h) -> int:

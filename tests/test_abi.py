@@ -136,6 +136,29 @@ def test_create_checks_before_gpu():
     assert L.lbm_load_state(None, buf, C.c_size_t(64)) == B.LBM_EINVAL
 
 
+def test_checkpoint_buffers_checked_in_the_binding():
+    """The library reads or writes buf.nbytes bytes from a buffer's first
+    element: the binding accepts only C-contiguous uint8 arrays (writable for
+    a save) and raises before any library call otherwise.  No GPU call."""
+    import numpy as np
+    good = np.zeros(64, dtype=np.uint8)
+    ro = good.copy()
+    ro.flags.writeable = False
+    for bad in (np.zeros(128, dtype=np.uint8)[::2], np.zeros(16, dtype=np.float32), ro, bytearray(64)):
+        with pytest.raises(ValueError):
+            B.lbm_save_state(None, bad)
+    for bad in (np.zeros(128, dtype=np.uint8)[::2], np.zeros(16, dtype=np.float32), bytearray(64)):
+        with pytest.raises(ValueError):
+            B.lbm_load_state(None, bad)
+    # a read-only checkpoint loads; a NULL handle is the library's EINVAL
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_load_state(None, ro)
+    assert e.value.status == B.LBM_EINVAL
+    with pytest.raises(B.LbmError) as e:
+        B.lbm_save_state(None, good)
+    assert e.value.status == B.LBM_EINVAL
+
+
 @pytest.mark.parametrize("storage,nz", [(B.LBM_F64, 255), (B.LBM_F32, 511), (B.LBM_BF16_DEV, 1023)])
 def test_maximum_lattice_sizes(storage, nz):
     """Planes are addressed by 32-bit byte offsets from a uniform base (a
