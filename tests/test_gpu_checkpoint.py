@@ -54,7 +54,7 @@ def _state(sim, two, fs):
 @pytest.mark.parametrize("case,storage", [("miscible", "f32"), ("miscible", "f16s"), ("miscible", "bf16"),
                                           ("species", "bf16s"), ("two-fluid", "bf16"), ("tensor", "f64"),
                                           ("freesurface", "f32"), ("freesurface", "bf16"),
-                                          ("freesurface", "f16s"), ("two-fluid", "bf16s")])
+                                          ("freesurface", "f16s"), ("two-fluid", "bf16s"), ("two-fluid", "f16")])
 def test_resume_is_bitwise(case, storage):
     from paper_0912_4230_amd.sim import Simulation
     p = _problem(case)
